@@ -1,0 +1,7 @@
+"""MI355X-native signature kernels by local Neumann-series propagation
+(arXiv 2502.20392).  The compute path is libsigk.so (hand-written HIP for
+gfx950) behind the C ABI of include/sigk.h; this package is its Python
+binding (PyTorch for device memory and streams) plus autograd wrappers."""
+from .api import (RaggedPlan, counters, gram, last_workspace, pair, ragged,  # noqa: F401
+                  workspace)
+from . import _lib  # noqa: F401

@@ -1,0 +1,218 @@
+"""Python interface to libsigk: signature kernels of time series on MI355X.
+
+PyTorch supplies device memory (FP64 CUDA/HIP tensors) and the current
+stream; every arithmetic step runs in libsigk's HIP kernels.  Paths are
+``[length, d]`` FP64 tensors (batches ``[n, length, d]``) on the GPU.
+
+* ``pair(x, y)``            k(x, y) (Definition 2.1), one value.
+* ``gram(X, Y=None)``       Gram matrix (Proposition A.3); symmetric if Y is None.
+* ``RaggedPlan``            a ragged batch of path pairs: one persistent launch,
+                            graph-capturable ``run``, and ``backward``.
+* ``ragged(pool, offsets, pairs)``  one-shot ragged batch.
+* ``counters(ws)``          cells, algorithmic flops and status of a call.
+
+``order`` is the number of coefficients kept per edge series (P).  With
+``order="auto"`` the call is repeated with larger P until the device reports
+no truncation warning (this synchronises).
+"""
+import ctypes
+import threading
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_tls = threading.local()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_paths(t, name, ndim):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims")
+    return t.contiguous()
+
+
+def workspace(nbytes, device):
+    """A caller-owned device workspace (uint8 tensor) of at least nbytes."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def last_workspace():
+    return getattr(_tls, "ws", None)
+
+
+def counters(ws=None):
+    """Read (cells, flops, status, order) of the last call that used ws (synchronises)."""
+    ws = ws if ws is not None else last_workspace()
+    c = _lib.Counters()
+    _lib.check(_lib.load().sigk_read_counters(_ptr(ws), ctypes.byref(c), _stream()))
+    return {"cells": int(c.cells), "flops": int(c.flops), "status": int(c.status),
+            "order": int(c.order)}
+
+
+def _auto(run, order, order_hint):
+    """Run `run(order)` (returns (result, ws)); escalate order on truncation warnings."""
+    if order != "auto":
+        res, ws = run(order)
+        _tls.ws = ws
+        return res
+    ladder = [p for p in _lib.ORDERS if p >= order_hint] or [_lib.ORDERS[-1]]
+    for i, p in enumerate(ladder):
+        res, ws = run(p)
+        _tls.ws = ws
+        st = counters(ws)["status"]
+        if st & _lib.ERR_WATCHDOG:
+            raise RuntimeError("libsigk: dependency wait timed out")
+        if not (st & _lib.WARN_TRUNC) or i == len(ladder) - 1:
+            return res
+
+
+def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
+         order_hint=6):
+    """k(x, y) for paths x [lx, d], y [ly, d] (FP64, on the GPU).  Returns a 0-d tensor."""
+    x = _check_paths(x, "x", 2)
+    y = _check_paths(y, "y", 2)
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same number of channels")
+    lib = _lib.load()
+
+    def run(p):
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth)
+        nb = ctypes.c_size_t()
+        _lib.check(lib.sigk_pair_workspace_size(x.shape[0], y.shape[0], x.shape[1],
+                                                ctypes.byref(o), ctypes.byref(nb)))
+        w = ws if ws is not None and ws.numel() >= nb.value else workspace(nb.value, x.device)
+        out = torch.empty((), dtype=torch.float64, device=x.device)
+        _lib.check(lib.sigk_pair(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1],
+                                 ctypes.byref(o), _ptr(out), _ptr(w), w.numel(), _stream()))
+        return out, w
+
+    return _auto(run, order, order_hint)
+
+
+def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
+         order_hint=6):
+    """Gram matrix G[i, j] = k(X_i, Y_j); X [nx, lx, d], Y [ny, ly, d].  Y=None: symmetric."""
+    X = _check_paths(X, "X", 3)
+    sym = Y is None
+    Y = X if sym else _check_paths(Y, "Y", 3)
+    if X.shape[2] != Y.shape[2]:
+        raise ValueError("X and Y must have the same number of channels")
+    lib = _lib.load()
+    nx, lx, d = X.shape
+    ny, ly, _ = Y.shape
+
+    def run(p):
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth)
+        nb = ctypes.c_size_t()
+        _lib.check(lib.sigk_gram_workspace_size(nx, ny, lx, ly, d, int(sym), ctypes.byref(o),
+                                                ctypes.byref(nb)))
+        w = ws if ws is not None and ws.numel() >= nb.value else workspace(nb.value, X.device)
+        G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
+        _lib.check(lib.sigk_gram(_ptr(X), nx, _ptr(Y), ny, lx, ly, d, int(sym), ctypes.byref(o),
+                                 _ptr(G), _ptr(w), w.numel(), _stream()))
+        return G, w
+
+    return _auto(run, order, order_hint)
+
+
+class RaggedPlan:
+    """A ragged batch of path pairs over one pool of concatenated paths.
+
+    offsets: host int64 [npaths+1] (first point of each path in the pool);
+    pairs: host int32 [npairs, 2] path ids; d: channels.  The plan owns a
+    workspace on ``device`` once ``upload`` (called by run/backward) ran.
+    """
+
+    def __init__(self, offsets, pairs, d, order=12, tol=None, tail_tol=None, grid=0,
+                 fixed_depth=False, device="cuda"):
+        lib = _lib.load()
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        self.d = int(d)
+        self.npairs = self.pairs.shape[0]
+        self.opts = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+        h = ctypes.c_void_p()
+        _lib.check(lib.sigk_plan_ragged(self.offsets.ctypes.data_as(ctypes.c_void_p),
+                                        self.offsets.shape[0] - 1, self.d,
+                                        self.pairs.ctypes.data_as(ctypes.c_void_p), self.npairs,
+                                        ctypes.byref(self.opts), ctypes.byref(h)))
+        self._h = h
+        self.cells = int(lib.sigk_plan_cells(h))
+        self.ws_bytes = int(lib.sigk_plan_workspace_size(h))
+        self.bwd_ws_bytes = int(lib.sigk_plan_backward_workspace_size(h))
+        self.device = torch.device(device)
+        self.ws = None
+        self._uploaded = None
+        self.order = lib.sigk_supported_order(self.opts.order)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().sigk_plan_destroy(h)
+            except Exception:
+                pass
+
+    def ensure_workspace(self, backward=False):
+        need = self.bwd_ws_bytes if backward else self.ws_bytes
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = workspace(need, self.device)
+            self._uploaded = None
+        if self._uploaded is None:
+            _lib.check(_lib.load().sigk_plan_upload(self._h, _ptr(self.ws), self.ws.numel(),
+                                                    _stream()))
+            # the plan's host tables must outlive the copy
+            torch.cuda.current_stream().synchronize()
+            self._uploaded = True
+        return self.ws
+
+    def run(self, pool, out=None):
+        """out[p] = k(pairs[p]) for pool [sum len, d]; no host-device copies (capturable
+        once the workspace exists)."""
+        pool = _check_paths(pool, "pool", 2)
+        ws = self.ensure_workspace()
+        if out is None:
+            out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
+        _lib.check(_lib.load().sigk_plan_run(self._h, _ptr(pool), _ptr(out), _ptr(ws),
+                                             ws.numel(), _stream()))
+        _tls.ws = ws
+        return out
+
+    def backward(self, pool, grad_out, grad_pool=None):
+        """grad_pool += d(sum_p grad_out[p] k_p)/d pool."""
+        pool = _check_paths(pool, "pool", 2)
+        grad_out = grad_out.contiguous().to(torch.float64)
+        ws = self.ensure_workspace(backward=True)
+        if grad_pool is None:
+            grad_pool = torch.zeros_like(pool)
+        _lib.check(_lib.load().sigk_plan_backward(self._h, _ptr(pool), _ptr(grad_out),
+                                                  _ptr(grad_pool), _ptr(ws), ws.numel(),
+                                                  _stream()))
+        _tls.ws = ws
+        return grad_pool
+
+
+def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False,
+           order_hint=6):
+    """k for each pair of paths of a concatenated pool (host offsets / pairs)."""
+    pool = _check_paths(pool, "pool", 2)
+
+    def run(p):
+        plan = RaggedPlan(offsets, pairs, pool.shape[1], p, tol, tail_tol, grid, fixed_depth,
+                          pool.device)
+        return plan.run(pool), plan.ws
+
+    return _auto(run, order, order_hint)

@@ -1,0 +1,164 @@
+// sigk_device.h -- device helpers for the gfx950 kernels of libsigk.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sigk.h"
+#include "sigk_internal.h"
+
+namespace sigk {
+
+// ---------------------------------------------------------------- constants
+// 1/i!
+__host__ __device__ constexpr double ifact(int i) {
+    double v = 1.0;
+    for (int q = 2; q <= i; ++q) v /= (double)q;
+    return v;
+}
+// n!/(n+r)! = 1/((n+1)(n+2)...(n+r)): weights of the integrated edge series
+// (the Hankel part of the cell map, from W of Proposition 2.8).
+__host__ __device__ constexpr double hank(int n, int r) {
+    double v = 1.0;
+    for (int q = 1; q <= r; ++q) v /= (double)(n + q);
+    return v;
+}
+
+// Algorithmic FP64 flops of one cell at edge order P with Neumann depth q
+// (terms n = 1..q applied) and d channels.  FMA counts 2.
+//   n = 0 : two edge evaluations, 2(P-1) FMA
+//   n >= 1: e_n = e_{n-1} c / n (2 mul), Toeplitz 2(P-n) FMA,
+//           Hankel sums 2(P-1) FMA, scaled add 2 FMA
+//   Delta : d FMA
+__host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
+    long long f = 4LL * (P - 1);
+    for (int n = 1; n <= q; ++n) f += 2 + 4LL * (P - n) + 4LL * (P - 1) + 4;
+    return f + 2LL * d;
+}
+
+// ---------------------------------------------------------------- lanes
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+    return (uint64_t)__builtin_amdgcn_ballot_w64(p);
+}
+
+// Lane i receives v from lane i-1; lane 0 receives `lane0` (DPP wave_shr:1).
+__device__ __forceinline__ double shift_up(double v, double lane0) {
+    const long long b = __double_as_longlong(v);
+    const long long o = __double_as_longlong(lane0);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), 0x138, 0xf, 0xf,
+                                               false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane i receives v from lane i+1; lane 63 receives `lane63` (DPP wave_shl:1).
+__device__ __forceinline__ double shift_down(double v, double lane63) {
+    const long long b = __double_as_longlong(v);
+    const long long o = __double_as_longlong(lane63);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), 0x130, 0xf, 0xf,
+                                               false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------- sync
+__device__ __forceinline__ unsigned load_status(WsHeader* h) {
+    return __hip_atomic_load(&h->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_status(WsHeader* h, unsigned bits) {
+    if (bits && lane_id() == 0)
+        __hip_atomic_fetch_or(&h->status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *flag >= need.  Returns false (and raises the watchdog bit for
+// everyone) if the wait exceeds `ticks` of the 100 MHz real-time counter, or
+// if another wave already raised it.
+__device__ bool wait_at_least(const int* flag, int need, WsHeader* h, long long ticks) {
+    int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(v) < need) {
+        const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(2);
+            v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (uniform(v) >= need) break;
+            if (uniform((int)(load_status(h) & SIGK_ERR_WATCHDOG))) return false;
+            const long long now = (long long)__builtin_amdgcn_s_memrealtime();
+            if (now - t0 > ticks) {
+                raise_status(h, SIGK_ERR_WATCHDOG);
+                return false;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+__device__ __forceinline__ void publish(int* flag, int value) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane_id() == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- geometry
+struct Geo {
+    const double* x;  // path along the columns (u direction)
+    const double* y;  // path along the rows (v direction)
+    int m, n;         // cells: columns, rows
+    int64_t front;    // frontier offset (doubles)
+    int64_t ckpt;     // checkpoint offset (doubles)
+    int prog;         // progress offset
+    int o1, o2;       // output slots
+};
+
+// Row i and column j of entry p of the upper triangle (i <= j) of an N x N
+// matrix enumerated row by row.
+__device__ __forceinline__ void tri_decode(int64_t p, int64_t N, int64_t& i, int64_t& j) {
+    const double b = 2.0 * (double)N + 1.0;
+    int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+    if (r < 0) r = 0;
+    if (r >= N) r = N - 1;
+    auto start = [N](int64_t q) { return q * N - q * (q - 1) / 2; };
+    while (r > 0 && start(r) > p) --r;
+    while (r + 1 < N && start(r + 1) <= p) ++r;
+    i = r;
+    j = r + (p - start(r));
+}
+
+__device__ Geo resolve(const FwdArgs& a, int pair, int P, int64_t ckpt_per_pair) {
+    Geo g;
+    if (a.mode == kModeGram) {
+        int64_t i, j;
+        if (a.symmetric) {
+            tri_decode(pair, a.nx, i, j);
+        } else {
+            i = pair / a.ny;
+            j = pair % a.ny;
+        }
+        g.x = a.X + i * a.lx * a.d;
+        g.y = a.Y + j * a.ly * a.d;
+        g.m = (int)a.lx - 1;
+        g.n = (int)a.ly - 1;
+        g.front = (int64_t)pair * (int64_t)g.m * P * (a.ckpt ? a.strips : 1);
+        g.ckpt = (int64_t)pair * ckpt_per_pair;
+        g.prog = pair * a.strips;
+        g.o1 = (int)(i * a.ny + j);
+        g.o2 = (a.symmetric && i != j) ? (int)(j * a.ny + i) : -1;
+    } else {
+        const PairDesc& p = a.desc[pair];
+        g.x = a.X + p.x_off;
+        g.y = a.Y + p.y_off;
+        g.m = p.lx - 1;
+        g.n = p.ly - 1;
+        g.front = p.front_off;
+        g.ckpt = p.ckpt_off;
+        g.prog = p.prog_off;
+        g.o1 = p.out_idx;
+        g.o2 = p.out_idx2;
+    }
+    return g;
+}
+
+}  // namespace sigk

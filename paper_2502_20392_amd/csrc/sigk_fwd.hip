@@ -1,0 +1,73 @@
+// sigk_fwd.hip -- persistent forward kernel: k(x, y) for many pairs.
+//
+// Work unit ("ticket") = one 64-row strip of one pair.  Workgroups (one
+// wavefront each) claim tickets from a global counter in an order in which
+// every strip's producer (the strip below it) has a smaller ticket, so a
+// waiting wave always waits on a wave that is already running (no deadlock
+// for any grid size).  Gram mode interleaves pairs strip-major (all pairs'
+// strip 0, then strip 1, ...); table mode takes the host-built order.
+//
+// Compiled once per (P, D) variant: -DSIGK_P=<order> -DSIGK_D=<channel bucket>.
+#include "sigk_strip.h"
+
+#ifndef SIGK_P
+#define SIGK_P 8
+#endif
+#ifndef SIGK_D
+#define SIGK_D 8
+#endif
+
+namespace sigk {
+
+template <int P, int D>
+__global__ void __launch_bounds__(kWave) fwd_kernel(FwdArgs a) {
+    __shared__ LdsStrip<P, D> L;
+    Acc acc;
+    const int lane = lane_id();
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&a.hdr->ticket, 1u);
+        t = (unsigned)uniform((int)t);
+        if ((int64_t)t >= a.ntickets) break;
+        if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
+        int pair, strip;
+        if (a.mode == kModeGram) {
+            pair = (int)((int64_t)t % a.npairs);
+            strip = (int)((int64_t)t / a.npairs);
+        } else {
+            pair = a.tickets[t].pair;
+            strip = a.tickets[t].strip;
+        }
+        Geo g = resolve(a, pair, P, 0);
+        StripCtx<P, D> S(a, g, L, acc, strip);
+        S.Fout = a.frontier + g.front;
+        S.Fin = S.Fout;
+        S.prog = a.progress + g.prog;
+        S.ck = nullptr;
+        S.ck_every = 1;
+        if (!S.sweep()) break;
+    }
+    if (lane == 0) {
+        atomicAdd(&a.hdr->cells, acc.cells);
+        atomicAdd(&a.hdr->flops, acc.flops);
+        if (acc.status) atomicOr(&a.hdr->status, acc.status);
+    }
+}
+
+#define SIGK_CAT3(a, b, c) a##b##_##c
+#define SIGK_NAME(pre, P, D) SIGK_CAT3(pre, P, D)
+
+hipError_t SIGK_NAME(launch_fwd_, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+int SIGK_NAME(occupancy_fwd_, SIGK_P, SIGK_D)() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<SIGK_P, SIGK_D>, kWave, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
+}  // namespace sigk

@@ -1,0 +1,106 @@
+// sigk_internal.h -- device/host structures shared by the kernels and the
+// C-ABI layer of libsigk.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sigk {
+
+constexpr int kWave = 64;   // one wavefront = one strip of 64 grid rows
+constexpr int kRing = 128;  // increment ring in LDS: columns [t-64, t+64)
+constexpr int kMaxP = 24;   // largest compiled edge order
+
+// Compiled (P, D) variants of the forward kernel: edge order P (coefficients
+// per edge series), channel bucket D (d <= D, padded with zeros).
+#define SIGK_FWD_VARIANTS(X) \
+    X(4, 8) X(5, 8) X(6, 8) X(8, 8) X(10, 8) X(12, 8) X(16, 8) X(20, 8) X(24, 8) \
+    X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) X(20, 16) X(24, 16) \
+    X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32) X(20, 32) X(24, 32)
+
+// Variants of the adjoint kernels.
+#define SIGK_BWD_VARIANTS(X) \
+    X(4, 8) X(5, 8) X(6, 8) X(8, 8) X(10, 8) X(12, 8) X(16, 8) \
+    X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) \
+    X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32)
+
+// Frontier chunk (columns per progress flag) for edge order P.
+__host__ __device__ constexpr int chunk_cols(int P) { return P <= 8 ? 64 : 32; }
+
+// Per-pair geometry for table mode (ragged batches).  Offsets in elements.
+struct PairDesc {
+    int64_t x_off;      // first double of path x in the pool
+    int64_t y_off;      // first double of path y in the pool
+    int64_t front_off;  // first double of this pair's frontier / checkpoint area
+    int64_t ckpt_off;   // first double of this pair's adjoint checkpoints
+    int32_t lx, ly;     // points
+    int32_t prog_off;   // first progress counter (one per strip)
+    int32_t out_idx;    // output slot
+    int32_t out_idx2;   // mirror output slot or -1
+    int32_t pad;
+};
+
+struct Ticket {
+    int32_t pair;
+    int32_t strip;
+};
+
+// Header at the start of every workspace.
+struct WsHeader {
+    unsigned status;           // SIGK_WARN_* / SIGK_ERR_* bits
+    unsigned ticket;           // next ticket (forward)
+    unsigned long long cells;  // cells evaluated
+    unsigned long long flops;  // algorithmic flops
+    unsigned order;            // compiled edge order used
+    unsigned ticket2;          // next ticket (adjoint)
+    unsigned pad[56];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+enum { kModeGram = 0, kModeTable = 1 };
+
+struct FwdArgs {
+    int mode;
+    int symmetric;
+    int d;
+    int strips;        // strips per pair (gram mode)
+    const double* X;   // gram: X batch; table: pool
+    const double* Y;   // gram: Y batch; table: pool
+    int64_t nx, ny, lx, ly;
+    int64_t npairs;
+    int64_t ntickets;
+    const PairDesc* desc;
+    const Ticket* tickets;
+    double* out;
+    double* frontier;
+    int* progress;
+    WsHeader* hdr;
+    double* ckpt;      // adjoint checkpoints (null: forward only)
+    double tol;        // Neumann depth tolerance; < 0 applies every term
+    double tail_tol;
+    int ckpt_every;    // steps between wave-state checkpoints (adjoint)
+    long long watchdog_ticks;  // 100 MHz ticks before a wait is abandoned
+};
+
+struct BwdArgs {
+    FwdArgs f;               // geometry, thresholds, checkpoints
+    const double* grad_out;  // [npairs]
+    double* gpool;           // [sum len][d] accumulated gradient
+    double* lam_front;       // adjoint frontier (one per pair, [m][P])
+    int* lam_prog;           // adjoint progress counters
+    double* gdx;             // [sum len][d] scratch: gradient w.r.t. increments
+};
+
+// Launchers implemented per variant (one translation unit each).
+#define SIGK_DECL_FWD(P, D) \
+    hipError_t launch_fwd_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_fwd_##P##_##D();
+SIGK_FWD_VARIANTS(SIGK_DECL_FWD)
+#undef SIGK_DECL_FWD
+#define SIGK_DECL_BWD(P, D) \
+    hipError_t launch_ckpt_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
+    hipError_t launch_bwd_##P##_##D(const BwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_bwd_##P##_##D();
+SIGK_BWD_VARIANTS(SIGK_DECL_BWD)
+#undef SIGK_DECL_BWD
+
+}  // namespace sigk
