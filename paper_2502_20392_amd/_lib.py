@@ -9,7 +9,7 @@ import os
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsigk.so")
+LIB_PATH = os.environ.get("SIGK_LIB") or os.path.join(_HERE, "libsigk.so")
 
 SIGK_OK = 0
 SIGK_EINVAL = -1

@@ -17,12 +17,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
-OUT = os.path.join(HERE, "libsigk.so")
-BUILD = os.path.join(ROOT, "_build")
+OUT = os.environ.get("SIGK_OUT") or os.path.join(HERE, "libsigk.so")
+BUILD = os.environ.get("SIGK_BUILD_DIR") or os.path.join(ROOT, "_build")
 
 ARCH = os.environ.get("SIGK_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+EXTRA = os.environ.get("SIGK_EXTRA_FLAGS", "").split()
+FLAGS = EXTRA + ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-I", INCLUDE]
 HEADERS = ["sigk_internal.h", "sigk_device.h", "sigk_strip.h", "sigk_adjoint.h"]

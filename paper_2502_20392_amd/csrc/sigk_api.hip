@@ -100,8 +100,15 @@ int device_wgs(int P, int D, bool bwd) {
 
 void fill_common(FwdArgs& a, const sigk_opts& o, int P, int64_t d) {
     const double tol = o.tol > 0 ? o.tol : std::ldexp(1.0, -53);
-    // fixed depth: a negative tolerance keeps every Neumann term
-    a.tol = (o.flags & SIGK_FLAG_FIXED_DEPTH) ? -1.0 : tol;
+    // Neumann term n bounded by |c|^n/(n!)^2 relative to the edge data; it is
+    // applied where |c| > tau_n = (tol (n!)^2)^(1/n).  Fixed depth: tau < 0.
+    double lf = 0.0;  // log n!
+    for (int n = 0; n < kMaxP; ++n) {
+        if (n > 0) lf += std::log((double)n);
+        double tau = n == 0 ? 0.0 : std::exp((std::log(tol) + 2.0 * lf) / (double)n);
+        tau *= 1.0 - 1e-12;  // round the bound outward
+        a.tau2[n] = (o.flags & SIGK_FLAG_FIXED_DEPTH) ? -1.0 : tau * tau;
+    }
     a.tail_tol = o.tail_tol > 0 ? o.tail_tol : std::ldexp(1.0, -50);
     a.d = (int)d;
     a.watchdog_ticks = 2000000000LL;  // 20 s of the 100 MHz counter

@@ -15,26 +15,6 @@ __host__ __device__ constexpr double ifact(int i) {
     for (int q = 2; q <= i; ++q) v /= (double)q;
     return v;
 }
-// n!/(n+r)! = 1/((n+1)(n+2)...(n+r)): weights of the integrated edge series
-// (the Hankel part of the cell map, from W of Proposition 2.8).
-__host__ __device__ constexpr double hank(int n, int r) {
-    double v = 1.0;
-    for (int q = 1; q <= r; ++q) v /= (double)(n + q);
-    return v;
-}
-
-// Algorithmic FP64 flops of one cell at edge order P with Neumann depth q
-// (terms n = 1..q applied) and d channels.  FMA counts 2.
-//   n = 0 : two edge evaluations, 2(P-1) FMA
-//   n >= 1: e_n = e_{n-1} c / n (2 mul), Toeplitz 2(P-n) FMA,
-//           Hankel sums 2(P-1) FMA, scaled add 2 FMA
-//   Delta : d FMA
-__host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
-    long long f = 4LL * (P - 1);
-    for (int n = 1; n <= q; ++n) f += 2 + 4LL * (P - n) + 4LL * (P - 1) + 4;
-    return f + 2LL * d;
-}
-
 // ---------------------------------------------------------------- lanes
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
 

@@ -7,7 +7,6 @@
 namespace sigk {
 
 constexpr int kWave = 64;   // one wavefront = one strip of 64 grid rows
-constexpr int kRing = 128;  // increment ring in LDS: columns [t-64, t+64)
 constexpr int kMaxP = 24;   // largest compiled edge order
 
 // Compiled (P, D) variants of the forward kernel: edge order P (coefficients
@@ -25,6 +24,9 @@ constexpr int kMaxP = 24;   // largest compiled edge order
 
 // Frontier chunk (columns per progress flag) for edge order P.
 __host__ __device__ constexpr int chunk_cols(int P) { return P <= 8 ? 64 : 32; }
+// Columns of the increment ring in LDS: it holds [c0-63, c0+chunk) while the
+// steps of chunk c0 run.
+__host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }
 
 // Per-pair geometry for table mode (ragged batches).  Offsets in elements.
 struct PairDesc {
@@ -75,7 +77,8 @@ struct FwdArgs {
     int* progress;
     WsHeader* hdr;
     double* ckpt;      // adjoint checkpoints (null: forward only)
-    double tol;        // Neumann depth tolerance; < 0 applies every term
+    double tau2[kMaxP];  // Neumann term n is needed where |c|^2 > tau2[n]
+                         // (|c|^n/(n!)^2 > tol); all < 0 for the fixed depth
     double tail_tol;
     int ckpt_every;    // steps between wave-state checkpoints (adjoint)
     long long watchdog_ticks;  // 100 MHz ticks before a wait is abandoned

@@ -17,20 +17,37 @@
 // coefficient, the entries of C = A o B o W give
 //     A'_i = sum_{n=0}^{i} e_n A_{i-n} + e_i * sum_{r>=1} B_r i!/(i+r)!
 //     B'_j = sum_{n=0}^{j} e_n B_{j-n} + e_j * sum_{r>=1} A_r j!/(j+r)!
-// with e_n = c^n/n!; A' is the top edge, B' the right edge.  Neumann term n
-// (the entries of C with min(i, j) = n, i.e. the n-th term of the series of
-// Prop. 2.5) is applied only while some lane of the wave has
-// |c|^n/(n!)^2 > tol, the bound of that term relative to the edge data.
+// with e_n = c^n/n!; A' is the top edge, B' the right edge.  The Hankel sums
+// are evaluated in nested (Horner) form, which needs only the constants 1/k.
+//
+// Neumann depth.  Term n (the entries of C with min(i, j) = n, the n-th term
+// of the series of Prop. 2.5) is bounded by |c|^n/(n!)^2 relative to the edge
+// data.  It is applied while |c| may exceed tau_n = (tol (n!)^2)^(1/n)
+// anywhere in the cells a chunk of 64 steps covers, using the exact bound
+// |c| = |<dx_k, dy_l>| <= |dx_k| |dy_l| (Cauchy-Schwarz).  The depth is
+// therefore uniform over the wave and known before each chunk, so the step
+// loop carries no data-dependent branch.
 #pragma once
 #include "sigk_device.h"
 
 namespace sigk {
 
+// Ring slot of column col (col >= -ring_cols(P)).
+template <int P>
+__device__ __forceinline__ int ring_slot(int col) {
+    constexpr int RB = ring_cols(P);
+    if constexpr ((RB & (RB - 1)) == 0)
+        return col & (RB - 1);
+    else
+        return (int)((unsigned)(col + RB) % (unsigned)RB);
+}
+
 template <int P, int D>
 struct LdsStrip {
-    double dx[D * kRing];                // increments of x, [channel][column mod 128]
-    double bin[chunk_cols(P) * P];       // bottom edges of the current chunk (lane 0)
-    double tout[chunk_cols(P) * P];      // top edges of the top lane, current chunk
+    double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
+    double nrm2[ring_cols(P)];      // |dx_k|^2 of the same columns
+    double bin[chunk_cols(P) * P];  // bottom edges of the current chunk (lane 0)
+    double tout[chunk_cols(P) * P]; // top edges of the top lane, current chunk
 };
 
 struct Acc {
@@ -38,69 +55,108 @@ struct Acc {
     unsigned status = 0;
 };
 
-// The truncated cell map.  Returns the Neumann depth applied (wave-uniform).
-// `live` is the mask of lanes whose cells are real (others carry garbage).
+// Reciprocals 1/k, k = 0..2P (entry 0 unused).  For mid-size P they are pinned
+// in vector registers (the wave runs alone on its SIMD there anyway), so the
+// hot loop neither rebuilds them nor spills them from scalar registers; for
+// small P the registers buy more occupancy instead.
 template <int P>
-__device__ __forceinline__ int cell_map(const double (&A)[P], double (&B)[P], double c,
-                                        double (&An)[P], double (&Bn)[P], double tol,
-                                        uint64_t live) {
-    B[0] = A[0];
-    An[0] = A[0];
-    Bn[0] = A[0];
+struct Recip {
+    double v[2 * P + 1];
+    __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int r = 1; r < P; ++r) {
-        An[0] = fma(ifact(r), B[r], An[0]);
-        Bn[0] = fma(ifact(r), A[r], Bn[0]);
+        for (int k = 0; k <= 2 * P; ++k) {
+            v[k] = k == 0 ? 0.0 : 1.0 / (double)k;
+            if (P >= 10 && P <= 12) asm volatile("" : "+v"(v[k]));
+        }
+    }
+    __device__ __forceinline__ double operator()(int k) const { return v[k]; }
+};
+
+// Algorithmic flops of one cell at edge order P, Neumann depth q, d channels
+// (FMA = 2 flops):
+//   n = 0 : two Horner edge evaluations, 2(P-2) FMA + 2 add       -> 4P - 6
+//   n >= 1: e_n (2 mul), Toeplitz 2(P-n) FMA, Horner sums 2(P-2) FMA,
+//           e_n/(n+1) (1 mul), 2 FMA                               -> 8P - 4n - 1
+//   Delta : d FMA                                                  -> 2d
+__host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
+    return 4LL * P - 6 + (long long)q * (8LL * P - 1) - 2LL * q * (q + 1) + 2LL * d;
+}
+
+// Neumann term N of the cell map (Toeplitz part and Horner-form Hankel part),
+// then the following terms while N < q.  Written as a compile-time recursion
+// so that every coefficient index is a constant (registers, never scratch).
+template <int P, int N>
+__device__ __forceinline__ void neumann_terms(const double (&A)[P], const double (&B)[P],
+                                              double c, double e, double (&An)[P],
+                                              double (&Bn)[P], int q, const Recip<P>& R) {
+    if constexpr (N < P) {
+        if (N > q) return;  // scalar, uniform (folds away for a constant q)
+        e = e * c * R(N);
+#pragma unroll
+        for (int i = N; i < P; ++i) {
+            An[i] = fma(e, A[i - N], An[i]);
+            Bn[i] = fma(e, B[i - N], Bn[i]);
+        }
+        // sum_{r>=1} B_r N!/(N+r)! = (1/(N+1)) [B_1 + (1/(N+2)) [B_2 + ...]]
+        double tb = B[P - 1], ta = A[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) {
+            tb = fma(tb, R(N + r + 1), B[r]);
+            ta = fma(ta, R(N + r + 1), A[r]);
+        }
+        const double en = e * R(N + 1);
+        An[N] = fma(en, tb, An[N]);
+        Bn[N] = fma(en, ta, Bn[N]);
+        neumann_terms<P, N + 1>(A, B, c, e, An, Bn, q, R);
+    }
+}
+
+// The truncated cell map with Neumann depth q (wave-uniform, q <= P-1).
+template <int P>
+__device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], double c,
+                                         double (&An)[P], double (&Bn)[P], int q,
+                                         const Recip<P>& R) {
+    B[0] = A[0];
+    // n = 0: corner values from the edges, sum_{r>=1} B_r/r! and sum A_r/r!
+    {
+        double tb = B[P - 1], ta = A[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) {
+            tb = fma(tb, R(r + 1), B[r]);
+            ta = fma(ta, R(r + 1), A[r]);
+        }
+        An[0] = A[0] + tb;
+        Bn[0] = A[0] + ta;
     }
 #pragma unroll
     for (int i = 1; i < P; ++i) {
         An[i] = A[i];
         Bn[i] = B[i];
     }
-    double e = 1.0;
-    int q = 0;
-#pragma unroll
-    for (int n = 1; n < P; ++n) {
-        e = e * c * (1.0 / (double)n);
-        // bound of Neumann term n relative to the edge data: |c|^n / (n!)^2
-        const double bound = fabs(e) * ifact(n);
-        if ((__builtin_amdgcn_fcmp(bound, tol, 2 /* ordered greater */) & live) == 0) break;
-        q = n;
-#pragma unroll
-        for (int i = n; i < P; ++i) {
-            An[i] = fma(e, A[i - n], An[i]);
-            Bn[i] = fma(e, B[i - n], Bn[i]);
-        }
-        double hb = 0.0, ha = 0.0;
-#pragma unroll
-        for (int r = 1; r < P; ++r) {
-            hb = fma(hank(n, r), B[r], hb);
-            ha = fma(hank(n, r), A[r], ha);
-        }
-        An[n] = fma(e, hb, An[n]);
-        Bn[n] = fma(e, ha, Bn[n]);
-    }
-    return q;
+    neumann_terms<P, 1>(A, B, c, 1.0, An, Bn, q, R);
 }
-
-__host__ __device__ constexpr long long cell_flops_q(int P, int q, int d) {
-    // closed form of cell_flops: 4(P-1) + sum_{n=1..q} (8P - 4n + 2) + 2d
-    return 4LL * (P - 1) + (long long)q * (8LL * P + 2) - 2LL * q * (q + 1) + 2LL * d;
-}
-static_assert(cell_flops_q(8, 5, 3) == cell_flops(8, 5, 3), "flop formula");
 
 // Edge-series tail check: last coefficient's weight against the edge norm.
 template <int P>
 __device__ __forceinline__ void tail_check(const double* v, double tail_tol, bool act,
                                            unsigned& status) {
-    double s = 0.0;
+    double s = 0.0, f = 1.0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) s = fma(fabs(v[i]), ifact(i), s);
-    const double tail = fabs(v[P - 1]) * ifact(P - 1);
+    for (int i = 0; i < P; ++i) {
+        s = fma(fabs(v[i]), f, s);
+        if (i + 1 < P) f = f / (double)(i + 1);
+    }
+    const double tail = fabs(v[P - 1]) * f;
     const bool bad_t = act && (tail > tail_tol * s);
     const bool bad_n = act && !isfinite(s);
     if (ballot(bad_t)) status |= SIGK_WARN_TRUNC;
     if (ballot(bad_n)) status |= SIGK_WARN_NONFINITE;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
 }
 
 template <int P, int D>
@@ -109,8 +165,8 @@ struct StripCtx {
     Geo& g;
     LdsStrip<P, D>& L;
     Acc& acc;
-    int s;            // strip index
-    int nrows;        // valid rows in this strip (<= 64)
+    int s;              // strip index
+    int nrows;          // valid rows in this strip (<= 64)
     bool lane_ok;
     bool has_below, has_above;
     const double* Fin;  // frontier row read by lane 0 ([m][P])
@@ -119,8 +175,11 @@ struct StripCtx {
     double B[P];        // left-edge series of the lane's current cell
     double Ac[P];       // top-edge series produced at the previous step
     double dy[D];
+    double dymax2;      // max_l |dy_l|^2 over the strip
+    int q;              // Neumann depth of the current chunk
     unsigned nvalid;
-    uint64_t okmask;   // lanes holding a grid row
+    uint64_t okmask;    // lanes holding a grid row
+    Recip<P> R;
     // checkpointing (adjoint support)
     double* ck;         // wave-state checkpoints of this strip or null
     int ck_every;
@@ -128,6 +187,8 @@ struct StripCtx {
     __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
 
+    // Load columns [c0, c0+CH) (increments, their norms, bottom edges) and set
+    // the Neumann depth for steps [c0, c0+CH).
     __device__ bool load_chunk(int c0) {
         const int lane = lane_id();
         const int CH = chunk_cols(P);
@@ -140,12 +201,26 @@ struct StripCtx {
         if (lane < nc) {
             const int col = c0 + lane;
             const double* xp = g.x + (int64_t)col * a.d;
+            double n2 = 0.0;
 #pragma unroll
-            for (int ch = 0; ch < D; ++ch)
-                L.dx[ch * kRing + (col & (kRing - 1))] =
-                    ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
+            for (int ch = 0; ch < D; ++ch) {
+                const double v = ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
+                L.dx[ch * ring_cols(P) + ring_slot<P>(col)] = v;
+                n2 = fma(v, v, n2);
+            }
+            L.nrm2[ring_slot<P>(col)] = n2;
         }
         __syncthreads();
+        // columns touched by steps [c0, c0+CH): [c0-63, c0+nc)
+        double w = 0.0;
+        const int k1 = c0 - (kWave - 1) + lane, k2 = c0 + lane;
+        if (k1 >= 0 && k1 < c0 + nc) w = L.nrm2[ring_slot<P>(k1)];
+        if (lane < nc) w = fmax(w, L.nrm2[ring_slot<P>(k2)]);
+        const double cmax2 = wave_max(w) * dymax2;
+        int qq = 0;
+#pragma unroll
+        for (int n = 1; n < P; ++n) qq = cmax2 > a.tau2[n] ? n : qq;
+        q = uniform(qq);
         return true;
     }
 
@@ -171,49 +246,99 @@ struct StripCtx {
         }
     }
 
+    // One step: every lane advances one cell along its row.  QC >= 0 fixes the
+    // Neumann depth at compile time (QC == q), QC < 0 reads q.
+    template <bool EDGE, int QC>
+    __device__ __forceinline__ void step(int t, bool act) {
+        const int lane = lane_id();
+        const int CH = chunk_cols(P);
+        const int col = t - lane;
+        double A[P];
+        const double* bsrc = &L.bin[(t % CH) * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
+        if (EDGE && col == 0) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+        }
+        const int ri = ring_slot<P>(col);
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < D; ch += 2) {
+            c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
+            c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+        }
+        double An[P], Bn[P];
+        cell_map<P>(A, B, c0 + c1, An, Bn, QC >= 0 ? QC : q, R);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            B[i] = Bn[i];
+            Ac[i] = An[i];
+        }
+        if (has_above && lane == kWave - 1 && act) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) L.tout[(col % CH) * P + i] = An[i];
+        }
+    }
+
+    // Steady-state steps [t, te) at the chunk's depth q.  For small orders the
+    // depth is dispatched to a loop specialised for it (no branch per term).
+    template <int QD>
+    __device__ __forceinline__ void run_depth(int& t, int te) {
+        if constexpr (P <= 8 && QD < P - 1) {
+            if (q > QD) {
+                run_depth<QD + 1>(t, te);
+                return;
+            }
+        }
+        constexpr int QC = P <= 8 ? QD : -1;
+        for (; t < te; ++t) {
+            if (ck && (t % ck_every) == 0) save_state(t);
+            step<false, QC>(t, lane_ok);
+        }
+    }
+
     template <bool EDGE>
     __device__ bool run(int t0, int t1) {
         const int lane = lane_id();
         const int CH = chunk_cols(P);
         const int m = g.m;
-        for (int t = t0; t < t1; ++t) {
+        int t = t0;
+        while (t < t1) {
             if ((t % CH) == 0 && t < m) {
                 if (!load_chunk(t)) return false;
-                if (t > 0) tail_check<P>(B, a.tail_tol, lane_ok && t - lane > 0 && t - lane <= m,
-                                         acc.status);
+                if (t > 0)
+                    tail_check<P>(B, a.tail_tol, lane_ok && t - lane > 0 && t - lane <= m,
+                                  acc.status);
             }
-            if (ck && (t % ck_every) == 0) save_state(t);
-            const int col = t - lane;
-            const bool act = EDGE ? (lane_ok && col >= 0 && col < m) : lane_ok;
-            const uint64_t live = EDGE ? ballot(act) : okmask;
-            double A[P];
-            const double* bsrc = &L.bin[(t % CH) * P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
-            if (EDGE && col == 0) {
-#pragma unroll
-                for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
-            }
-            const int ri = col & (kRing - 1);
-            double c = 0.0;
-#pragma unroll
-            for (int ch = 0; ch < D; ++ch) c = fma(dy[ch], L.dx[ch * kRing + ri], c);
-            double An[P], Bn[P];
-            const int q = cell_map<P>(A, B, c, An, Bn, a.tol, live);
-#pragma unroll
-            for (int i = 0; i < P; ++i) {
-                B[i] = Bn[i];
-                Ac[i] = An[i];
-            }
-            const unsigned cnt = EDGE ? (unsigned)__builtin_popcountll(live) : nvalid;
-            acc.cells += cnt;
-            acc.flops += (unsigned long long)cnt * (unsigned long long)cell_flops_q(P, q, a.d);
+            // steps up to the next chunk boundary, flush point or range end
+            int te = min(t1, t - (t % CH) + CH);
             if (has_above) {
-                if (lane == kWave - 1 && act) {
-#pragma unroll
-                    for (int i = 0; i < P; ++i) L.tout[(col % CH) * P + i] = An[i];
-                }
+                // the top lane finishes column tc at step tc + 63
                 const int tc = t - (kWave - 1);
+                const int nxt = tc < 0 ? CH - 1 : tc - (tc % CH) + CH - 1;
+                te = min(te, min(nxt, m - 1) + kWave);
+            }
+            if (ck) te = min(te, t - (t % ck_every) + ck_every);
+            const long long fl = cell_flops(P, q, a.d);
+            if (EDGE) {
+                for (; t < te; ++t) {
+                    if (ck && (t % ck_every) == 0) save_state(t);
+                    const int col = t - lane;
+                    const bool act = lane_ok && col >= 0 && col < m;
+                    const unsigned cnt = (unsigned)__builtin_popcountll(ballot(act));
+                    acc.cells += cnt;
+                    acc.flops += (unsigned long long)cnt * (unsigned long long)fl;
+                    step<true, -1>(t, act);
+                }
+            } else {
+                const int n = te - t;
+                acc.cells += (unsigned long long)n * nvalid;
+                acc.flops += (unsigned long long)n * nvalid * (unsigned long long)fl;
+                run_depth<0>(t, te);
+            }
+            if (has_above) {
+                const int tc = t - 1 - (kWave - 1);
                 if (tc >= 0 && tc < m && ((tc % CH) == CH - 1 || tc == m - 1))
                     flush(tc - tc % CH, tc + 1);
             }
@@ -232,12 +357,18 @@ struct StripCtx {
         has_above = row0 + kWave < g.n;
         nvalid = (unsigned)nrows;
         okmask = ballot(lane_ok);
+        R.init();
         const int l = row0 + lane;
+        double n2 = 0.0;
 #pragma unroll
-        for (int ch = 0; ch < D; ++ch)
+        for (int ch = 0; ch < D; ++ch) {
             dy[ch] = (ch < a.d && lane_ok)
                          ? g.y[(int64_t)(l + 1) * a.d + ch] - g.y[(int64_t)l * a.d + ch]
                          : 0.0;
+            n2 = fma(dy[ch], dy[ch], n2);
+        }
+        dymax2 = wave_max(n2);
+        q = P - 1;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             B[i] = i == 0 ? 1.0 : 0.0;
@@ -260,9 +391,12 @@ struct StripCtx {
             const bool mine = lane == nrows - 1;
             tail_check<P>(Ac, a.tail_tol, mine, acc.status);
             if (mine) {
-                double k = 0.0;
+                double k = 0.0, f = 1.0;
 #pragma unroll
-                for (int i = P - 1; i >= 0; --i) k = fma(Ac[i], ifact(i), k);
+                for (int i = 0; i < P; ++i) {
+                    k = fma(Ac[i], f, k);
+                    f = f / (double)(i + 1);
+                }
                 a.out[g.o1] = k;
                 if (g.o2 >= 0) a.out[g.o2] = k;
             }
