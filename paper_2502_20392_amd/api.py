@@ -216,3 +216,109 @@ def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixe
         return plan.run(pool), plan.ws
 
     return _auto(run, order, order_hint)
+
+
+# ------------------------------------------------------------------ autograd
+
+def _pool_and_pairs(X, Y, symmetric):
+    """Pool [X; Y] (paths back to back) and the pair table of a Gram matrix."""
+    nx, lx, d = X.shape
+    if symmetric:
+        pool = X.reshape(-1, d)
+        offsets = np.arange(nx + 1, dtype=np.int64) * lx
+        ii, jj = np.triu_indices(nx)
+        pairs = np.stack([ii, jj], axis=1).astype(np.int32)
+    else:
+        ny, ly, _ = Y.shape
+        pool = torch.cat([X.reshape(-1, d), Y.reshape(-1, d)], dim=0)
+        offsets = np.concatenate([np.arange(nx + 1) * lx,
+                                  nx * lx + np.arange(1, ny + 1) * ly]).astype(np.int64)
+        ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+        pairs = np.stack([ii.ravel(), nx + jj.ravel()], axis=1).astype(np.int32)
+    return pool.contiguous(), offsets, pairs
+
+
+class _GramFunction(torch.autograd.Function):
+    """G = [k(X_i, Y_j)] with the adjoint sweep as backward."""
+
+    @staticmethod
+    def forward(ctx, X, Y, order, tol, symmetric):
+        pool, offsets, pairs = _pool_and_pairs(X, Y, symmetric)
+        plan = RaggedPlan(offsets, pairs, X.shape[2], order=order, tol=tol, device=X.device)
+        vals = plan.run(pool)
+        nx = X.shape[0]
+        ny = nx if symmetric else Y.shape[0]
+        G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
+        if symmetric:
+            ii, jj = pairs[:, 0], pairs[:, 1]
+            G[ii, jj] = vals
+            G[jj, ii] = vals
+        else:
+            G.view(-1).copy_(vals)
+        ctx.plan, ctx.pool, ctx.pairs, ctx.symmetric = plan, pool, pairs, symmetric
+        ctx.shapes = (X.shape, None if symmetric else Y.shape)
+        return G
+
+    @staticmethod
+    def backward(ctx, gG):
+        gG = gG.contiguous()
+        pairs = ctx.pairs
+        if ctx.symmetric:
+            ii = torch.from_numpy(pairs[:, 0].astype(np.int64)).to(gG.device)
+            jj = torch.from_numpy(pairs[:, 1].astype(np.int64)).to(gG.device)
+            w = gG[ii, jj] + gG[jj, ii]
+            w = torch.where(ii == jj, gG[ii, jj], w)
+        else:
+            w = gG.reshape(-1)
+        gpool = ctx.plan.backward(ctx.pool, w.contiguous())
+        xs, ys = ctx.shapes
+        nxp = xs[0] * xs[1]
+        gX = gpool[:nxp].reshape(xs)
+        gY = None if ctx.symmetric else gpool[nxp:].reshape(ys)
+        return gX, gY, None, None, None
+
+
+def sigkernel_gram(X, Y=None, order=12, tol=None):
+    """Differentiable Gram matrix of signature kernels (FP64, GPU)."""
+    X = _check_paths(X, "X", 3)
+    if Y is None:
+        return _GramFunction.apply(X, None, order, tol, True)
+    Y = _check_paths(Y, "Y", 3)
+    return _GramFunction.apply(X, Y, order, tol, False)
+
+
+class _MMD2Function(torch.autograd.Function):
+    """Biased MMD^2 = mean k(X,X) + mean k(Y,Y) - 2 mean k(X,Y) in one ragged launch."""
+
+    @staticmethod
+    def forward(ctx, X, Y, order, tol):
+        nx, lx, d = X.shape
+        ny, ly, _ = Y.shape
+        pool = torch.cat([X.reshape(-1, d), Y.reshape(-1, d)], dim=0).contiguous()
+        offsets = np.concatenate([np.arange(nx + 1) * lx,
+                                  nx * lx + np.arange(1, ny + 1) * ly]).astype(np.int64)
+        xi, xj = np.triu_indices(nx)
+        yi, yj = np.triu_indices(ny)
+        ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+        pairs = np.concatenate([np.stack([xi, xj], 1), np.stack([nx + yi, nx + yj], 1),
+                                np.stack([ci.ravel(), nx + cj.ravel()], 1)]).astype(np.int32)
+        w = np.concatenate([np.where(xi == xj, 1.0, 2.0) / (nx * nx),
+                            np.where(yi == yj, 1.0, 2.0) / (ny * ny),
+                            np.full(nx * ny, -2.0 / (nx * ny))])
+        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
+        vals = plan.run(pool)
+        wt = torch.from_numpy(w).to(X.device)
+        ctx.plan, ctx.pool, ctx.wt, ctx.shapes = plan, pool, wt, (X.shape, Y.shape)
+        return (vals * wt).sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        gpool = ctx.plan.backward(ctx.pool, (ctx.wt * g).contiguous())
+        xs, ys = ctx.shapes
+        nxp = xs[0] * xs[1]
+        return gpool[:nxp].reshape(xs), gpool[nxp:].reshape(ys), None, None
+
+
+def mmd2(X, Y, order=12, tol=None):
+    """Differentiable biased MMD^2 between path sets X [nx, lx, d] and Y [ny, ly, d]."""
+    return _MMD2Function.apply(_check_paths(X, "X", 3), _check_paths(Y, "Y", 3), order, tol)

@@ -1,0 +1,120 @@
+// sigk_adjoint.h -- reverse (adjoint) wavefront sweep of one 64-row strip.
+//
+// The forward cell map is linear in the edge data:
+//     A'_i = sum_{n<=min(i,q)} e_n A_{i-n} + [i<=q] e_i hB_i,
+//     B'_j = sum_{n<=min(j,q)} e_n B_{j-n} + [j<=q] e_j hA_j,
+// with B_0 := A_0, e_n = c^n/n! and hB_n = sum_{r>=1} B_r n!/(n+r)!.  Its
+// adjoint maps the cotangents (lA', lB') of the top and right edges to those
+// of the bottom and left edges, and to dL/dc:
+//     lA_r = sum_n e_n lA'_{r+n} + [r>=1] sum_{n<=q} e_n n!/(n+r)! lB'_n
+//            (+ sum_n e_n lB'_n   for r = 0, through B_0 := A_0)
+//     lB_r = sum_n e_n lB'_{r+n} + sum_{n<=q} e_n n!/(n+r)! lA'_n      (r >= 1)
+//     dL/dc = sum_{n=1}^{q} e_{n-1} [ sum_{i>=n} (lA'_i A_{i-n} + lB'_i B_{i-n})
+//                                     + lA'_n hB_n + lB'_n hA_n ].
+// This is the exact gradient of the truncated forward map (the depth q is a
+// piecewise-constant choice and carries no derivative).  In the limit of full
+// depth it is the Riemann-function form of the derivative of the Volterra
+// equation of Sec. 2.1.
+//
+// Cotangents flow in reverse topological order: the top-edge cotangent of
+// cell (k, l) is the bottom-edge cotangent of cell (k, l+1), the right-edge
+// cotangent is the left-edge cotangent of cell (k+1, l).  In the strip's
+// step coordinates the adjoint of step t runs after that of step t+1, so lane
+// j receives lA' from lane j+1 by a DPP shift, and lB' stays in the lane.
+#pragma once
+#include "sigk_strip.h"
+
+namespace sigk {
+
+// Hankel sums hB_n, hA_n for n = N..q (Horner form, as in the forward).
+template <int P, int N>
+__device__ __forceinline__ void hankel_sums(const double (&A)[P], const double (&B)[P], int q,
+                                            double (&hA)[P], double (&hB)[P],
+                                            const Recip<P>& R) {
+    if constexpr (N < P) {
+        if (N > q) return;
+        double tb = B[P - 1], ta = A[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) {
+            tb = fma(tb, R(N + r + 1), B[r]);
+            ta = fma(ta, R(N + r + 1), A[r]);
+        }
+        hB[N] = tb * R(N + 1);
+        hA[N] = ta * R(N + 1);
+        hankel_sums<P, N + 1>(A, B, q, hA, hB, R);
+    }
+}
+
+// Term N >= 1 of the adjoint: Toeplitz transposes, Hankel transposes and the
+// dL/dc contribution.  e = e_{N-1} on entry.
+template <int P, int N>
+__device__ __forceinline__ void adjoint_terms(const double (&A)[P], const double (&B)[P],
+                                              double c, double e, int q, const double (&hA)[P],
+                                              const double (&hB)[P], const double (&lAo)[P],
+                                              const double (&lBo)[P], double (&lA)[P],
+                                              double (&lB)[P], double& g, const Recip<P>& R) {
+    if constexpr (N < P) {
+        if (N > q) return;
+        const double ep = e;             // e_{N-1} = d e_N / dc
+        const double en = e * c * R(N);  // e_N
+        double corr = fma(lAo[N], hB[N], lBo[N] * hA[N]);
+#pragma unroll
+        for (int r = 0; r + N < P; ++r) {
+            lA[r] = fma(en, lAo[r + N], lA[r]);
+            lB[r] = fma(en, lBo[r + N], lB[r]);  // r = 0 entry: cotangent of B_0 := A_0
+            corr = fma(lAo[r + N], A[r], corr);
+            corr = fma(lBo[r + N], B[r], corr);
+        }
+        g = fma(ep, corr, g);
+        // Hankel transposes: weights e_N N!/(N+r)! as a running product
+        double wa = en * lAo[N] * R(N + 1);
+        double wb = en * lBo[N] * R(N + 1);
+#pragma unroll
+        for (int r = 1; r < P; ++r) {
+            lB[r] += wa;
+            lA[r] += wb;
+            wa *= R(N + r + 1);
+            wb *= R(N + r + 1);
+        }
+        adjoint_terms<P, N + 1>(A, B, c, en, q, hA, hB, lAo, lBo, lA, lB, g, R);
+    }
+}
+
+// Adjoint of cell_map.  A, Bin: the cell's inputs; lAo, lBo: cotangents of its
+// outputs.  Writes the input cotangents lA, lB and returns dL/dc.
+template <int P>
+__device__ __forceinline__ double cell_adjoint(const double (&A)[P], const double (&Bin)[P],
+                                               double c, int q, const double (&lAo)[P],
+                                               const double (&lBo)[P], double (&lA)[P],
+                                               double (&lB)[P], const Recip<P>& R) {
+    double B[P];
+    B[0] = A[0];
+#pragma unroll
+    for (int r = 1; r < P; ++r) B[r] = Bin[r];
+    double hA[P], hB[P];
+    hankel_sums<P, 1>(A, B, q, hA, hB, R);
+    // n = 0 terms: identity parts and the constant-term Hankel rows
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        lA[r] = lAo[r];
+        lB[r] = lBo[r];
+    }
+    {
+        double wa = lAo[0], wb = lBo[0];
+#pragma unroll
+        for (int r = 1; r < P; ++r) {
+            wa *= R(r);
+            wb *= R(r);
+            lB[r] += wa;  // d A'_0 / d B_r = 1/r!
+            lA[r] += wb;  // d B'_0 / d A_r = 1/r!
+        }
+    }
+    double g = 0.0;
+    adjoint_terms<P, 1>(A, B, c, 1.0, q, hA, hB, lAo, lBo, lA, lB, g, R);
+    // B_0 := A_0: its cotangent goes to A_0
+    lA[0] += lB[0];
+    lB[0] = 0.0;
+    return g;
+}
+
+}  // namespace sigk

@@ -20,7 +20,6 @@ using namespace sigk;
 namespace {
 
 constexpr int kOrders[] = {4, 5, 6, 8, 10, 12, 16, 20, 24};
-constexpr int kBwdMaxOrder = 16;
 constexpr int kDims[] = {8, 16, 32};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -181,17 +180,18 @@ struct sigk_plan {
     int64_t snap_doubles = 0;         // adjoint: per-strip frontier snapshots
     int64_t ckpt_doubles = 0;         // adjoint: wave-state checkpoints
     int64_t pool_points = 0;
-    int ckpt_every = 4;
+    int bwd_grid = 0;                 // workgroups the adjoint scratch is sized for
     uint64_t cells = 0;
     sigk_opts opts;
     // workspace offsets (bytes)
     size_t o_desc = 0, o_tk = 0, o_tkr = 0, o_prog = 0, o_front = 0, fwd_total = 0;
-    size_t o_snap = 0, o_ckpt = 0, o_lfront = 0, o_lprog = 0, o_gdx = 0, bwd_total = 0;
+    size_t o_snap = 0, o_ckpt = 0, o_lfront = 0, o_lprog = 0, o_gdx = 0, o_scr = 0,
+           bwd_total = 0;
 };
 
 namespace {
 
-int ckpt_every_for(int P) { return P <= 8 ? 4 : 2; }
+constexpr int kBwdMaxGrid = 2048;
 
 void plan_layout(sigk_plan& p) {
     size_t o = align256(sizeof(WsHeader));
@@ -217,6 +217,9 @@ void plan_layout(sigk_plan& p) {
     o = align256(o + sizeof(int) * (size_t)std::max<int64_t>(p.nprog, 1));
     p.o_gdx = o;
     o = align256(o + sizeof(double) * (size_t)std::max<int64_t>(p.pool_points * p.d, 1));
+    p.o_scr = o;
+    p.bwd_grid = kBwdMaxGrid;
+    o = align256(o + sizeof(double) * (size_t)p.bwd_grid * kCkptEvery * 2 * p.P * kWave);
     p.bwd_total = o;
 }
 
@@ -355,7 +358,6 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     pl->npairs = npairs;
     pl->opts = op;
     pl->pool_points = offsets[npaths];
-    pl->ckpt_every = ckpt_every_for(P);
     pl->desc.resize((size_t)npairs);
     std::vector<int> strips((size_t)npairs, 0);
     int64_t prog = 0, front = 0, snap = 0, ck = 0;
@@ -377,10 +379,10 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
         prog += S;
         q.front_off = front;
         front += m * P;
-        // adjoint: snapshot rows per strip and wave-state checkpoints
+        // adjoint: frontier snapshot per strip and wave-state checkpoints
         q.ckpt_off = ck;
-        const int64_t steps = m + kWave;  // >= m + nrows - 1 + 1
-        ck += (int64_t)S * ((steps + pl->ckpt_every - 1) / pl->ckpt_every + 1) * 2 * P * kWave;
+        ck += (int64_t)S * ckpt_strip_doubles(m, P);
+        q.snap_off = snap;
         snap += (int64_t)S * m * P;
         pl->cells += (uint64_t)(m * n);
     }
@@ -412,6 +414,32 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     *plan = pl;
     return SIGK_OK;
 }
+
+namespace {
+
+__global__ void zero_kernel(int* ip, int64_t ni, double* dp, int64_t nd) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < ni; i += stride) ip[i] = 0;
+    for (int64_t i = i0; i < nd; i += stride) dp[i] = 0.0;
+}
+
+// dL/dz_p = dL/d(dz_{p-1}) - dL/d(dz_p): increments dz_p = z_{p+1} - z_p are
+// stored at their first point; the last point of every path holds zero, so
+// the rule needs no path boundaries.
+__global__ void chain_kernel(const double* gdx, double* gpool, int64_t npts, int d) {
+    const int64_t n = npts * d;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < n; i += stride) {
+        const double prev = i >= d ? gdx[i - d] : 0.0;
+        gpool[i] += prev - gdx[i];
+    }
+}
+
+int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+}  // namespace
 
 void sigk_plan_destroy(sigk_plan* plan) { delete plan; }
 
@@ -520,12 +548,66 @@ int sigk_read_status(const void* ws, uint32_t* status_bits, void* stream) {
 
 }  // extern "C"
 
-// The adjoint entry point lives in sigk_bwd_api.hip.
-int sigk_plan_backward_impl(const sigk_plan* plan, const double* pool, const double* grad_out,
-                            double* grad_pool, void* ws, size_t ws_bytes, void* stream);
-
 extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
                                   const double* grad_out, double* grad_pool, void* ws,
                                   size_t ws_bytes, void* stream) {
-    return sigk_plan_backward_impl(plan, pool, grad_out, grad_pool, ws, ws_bytes, stream);
+    if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
+        return SIGK_EINVAL;
+    if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
+    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
+    const Variant* v = find_bwd(plan->P, plan->D);
+    if (!v) return SIGK_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    WsHeader* hdr = (WsHeader*)base;
+    int* prog = (int*)(base + plan->o_prog);
+    int* lprog = (int*)(base + plan->o_lprog);
+    double* gdx = (double*)(base + plan->o_gdx);
+    const int64_t ngdx = plan->pool_points * plan->d;
+    hipError_t e = launch_reset(hdr, prog, plan->nprog, nullptr, 0, (unsigned)plan->P, s);
+    if (e != hipSuccess) return device_error(e);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(std::max(plan->nprog, ngdx))), dim3(256), 0,
+                       s, lprog, plan->nprog, gdx, ngdx);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    // checkpointing forward pass
+    FwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_common(a, plan->opts, plan->P, plan->d);
+    a.mode = kModeTable;
+    a.X = pool;
+    a.Y = pool;
+    a.npairs = plan->npairs;
+    a.ntickets = (int64_t)plan->tickets.size();
+    a.desc = (const PairDesc*)(base + plan->o_desc);
+    a.tickets = (const Ticket*)(base + plan->o_tk);
+    a.out = nullptr;
+    a.frontier = (double*)(base + plan->o_snap);
+    a.progress = prog;
+    a.hdr = hdr;
+    a.ckpt = (double*)(base + plan->o_ckpt);
+    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, false);
+    grid = (int)std::min<int64_t>(grid, a.ntickets);
+    e = v->ckpt(a, std::max(grid, 1), s);
+    if (e != hipSuccess) return device_error(e);
+    // adjoint sweep
+    BwdArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.f = a;
+    b.tickets = (const Ticket*)(base + plan->o_tkr);
+    b.ntickets = (int64_t)plan->tickets_rev.size();
+    b.grad_out = grad_out;
+    b.snap = (double*)(base + plan->o_snap);
+    b.ckpt = (double*)(base + plan->o_ckpt);
+    b.lam_front = (double*)(base + plan->o_lfront);
+    b.lam_prog = lprog;
+    b.gdx = gdx;
+    b.scratch = (double*)(base + plan->o_scr);
+    int bgrid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, true);
+    bgrid = (int)std::min<int64_t>(std::min(bgrid, plan->bwd_grid), b.ntickets);
+    e = v->bwd(b, std::max(bgrid, 1), s);
+    if (e != hipSuccess) return device_error(e);
+    hipLaunchKernelGGL(chain_kernel, dim3(blocks_for(ngdx)), dim3(256), 0, s, gdx, grad_pool,
+                       plan->pool_points, (int)plan->d);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    return SIGK_OK;
 }

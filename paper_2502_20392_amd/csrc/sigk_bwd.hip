@@ -1,6 +1,21 @@
-// sigk_bwd.hip -- adjoint (reverse wavefront) kernels.  Placeholder until the
-// adjoint sweep lands: every launcher reports "not supported".
-#include "sigk_strip.h"
+// sigk_bwd.hip -- gradient of kernel values with respect to the paths.
+//
+// Two persistent kernels per (P, D) variant:
+//   ckpt_kernel: the forward sweep of every strip, keeping (a) the frontier row
+//                each strip reads (one snapshot per strip instead of the single
+//                in-place row), (b) the wave state (left edges and in-flight top
+//                edges of all 64 lanes) every kCkptEvery steps and (c) the
+//                Neumann depth of every chunk.
+//   bwd_kernel:  the adjoint sweep, strips in reverse topological order (top
+//                strip of each pair first).  Per segment of kCkptEvery steps,
+//                taken last to first: restore the wave state, recompute the
+//                segment forward while storing each step's cell inputs in a
+//                per-workgroup scratch, then run the adjoint cell map over the
+//                segment in reverse step order.  dL/dc of every cell is chained
+//                into dL/d(increment) of both paths: the x side through an LDS
+//                ring indexed by column (each column is complete once lane 0 has
+//                passed it), the y side in registers of the row's lane.
+#include "sigk_adjoint.h"
 
 #ifndef SIGK_P
 #define SIGK_P 8
@@ -10,13 +25,370 @@
 #endif
 
 namespace sigk {
+
+template <int P, int D>
+__global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
+    __shared__ LdsStrip<P, D> L;
+    Acc acc;
+    const int lane = lane_id();
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&a.hdr->ticket, 1u);
+        t = (unsigned)uniform((int)t);
+        if ((int64_t)t >= a.ntickets) break;
+        if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
+        const int pair = a.tickets[t].pair, strip = a.tickets[t].strip;
+        Geo g = resolve(a, pair, P, 0);
+        const PairDesc& pd = a.desc[pair];
+        StripCtx<P, D> S(a, g, L, acc, strip);
+        const int64_t row = (int64_t)g.m * P;
+        S.Fin = snap + pd.snap_off + (int64_t)strip * row;
+        S.Fout = snap + pd.snap_off + (int64_t)(strip + 1) * row;
+        S.prog = a.progress + g.prog;
+        double* ck = a.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
+        S.ck = ck;
+        S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
+        S.ck_every = kCkptEvery;
+        if (!S.sweep()) break;
+    }
+    if (lane == 0) {
+        atomicAdd(&a.hdr->cells, acc.cells);
+        atomicAdd(&a.hdr->flops, acc.flops);
+        if (acc.status) atomicOr(&a.hdr->status, acc.status);
+    }
+}
+
+template <int P, int D>
+struct LdsBwd {
+    double dx[D * ring_cols(P)];      // increments of x by ring slot
+    double gx[D * ring_cols(P)];      // dL/d(dx) being accumulated, by ring slot
+    double bin[chunk_cols(P) * P];    // primal bottom edges (lane 0) of a chunk
+    double lin[2 * chunk_cols(P) * P];  // top-edge cotangents (top lane), 2 chunks
+    double lout[chunk_cols(P) * P];   // bottom-edge cotangents (lane 0), 1 chunk
+};
+
+template <int P, int D>
+struct StripBwd {
+    const BwdArgs& b;
+    const FwdArgs& a;
+    Geo& g;
+    LdsBwd<P, D>& L;
+    int s, nrows, m;
+    bool lane_ok, has_below, has_above;
+    const PairDesc* pd;
+    double dy[D];
+    double gy[D];
+    Recip<P> R;
+    int dx_lo, lin_lo, bin_chunk;
+    double* scratch;
+    const double* ck;
+    const double* ckq;
+    const double* snap_in;   // primal frontier row read by lane 0 ([m][P])
+    double* lam_row;         // adjoint frontier row of the pair ([m][P])
+    int* lam_prog;           // adjoint progress of the pair's strips
+    double seed_scale;       // grad_out of the pair
+
+    __device__ StripBwd(const BwdArgs& b_, Geo& g_, LdsBwd<P, D>& L_, int s_)
+        : b(b_), a(b_.f), g(g_), L(L_), s(s_) {}
+
+    // Increments of x in steps of kCkptEvery columns, descending, so that the
+    // ring holds [t0-63, t0+kCkptEvery) for segment t0 (and never more than
+    // 63 + chunk columns of pending dL/d(dx) share its slots).
+    __device__ void load_dx_down_to(int lo_needed) {
+        const int lane = lane_id();
+        while (dx_lo > lo_needed && dx_lo > 0) {
+            const int c0 = max(dx_lo - kCkptEvery, 0);
+            const int col = c0 + lane;
+            if (col < dx_lo && col < m) {
+                const double* xp = g.x + (int64_t)col * a.d;
+#pragma unroll
+                for (int ch = 0; ch < D; ++ch)
+                    L.dx[ch * ring_cols(P) + ring_slot<P>(col)] =
+                        ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
+            }
+            dx_lo = c0;
+            __syncthreads();
+        }
+    }
+
+    __device__ bool load_lin_down_to(int lo_needed) {
+        const int CH = chunk_cols(P);
+        const int lane = lane_id();
+        while (lin_lo > lo_needed && lin_lo > 0) {
+            const int c0 = lin_lo - CH;
+            const int nc = min(CH, m - c0);
+            if (!wait_at_least(&lam_prog[s + 1], m - c0, a.hdr, a.watchdog_ticks)) return false;
+            double* dst = &L.lin[((c0 / CH) & 1) * CH * P];
+            const double* src = lam_row + (int64_t)c0 * P;
+            for (int e = lane; e < nc * P; e += kWave) dst[e] = src[e];
+            lin_lo = c0;
+            __syncthreads();
+        }
+        return true;
+    }
+
+    __device__ void load_bin(int chunk) {
+        const int CH = chunk_cols(P);
+        const int lane = lane_id();
+        const int c0 = chunk * CH;
+        const int nc = min(CH, m - c0);
+        if (has_below) {
+            const double* src = snap_in + (int64_t)c0 * P;
+            for (int e = lane; e < nc * P; e += kWave) L.bin[e] = src[e];
+        } else {
+            for (int e = lane; e < CH * P; e += kWave) L.bin[e] = (e % P) == 0 ? 1.0 : 0.0;
+        }
+        bin_chunk = chunk;
+        __syncthreads();
+    }
+
+    // columns [c0, c1) are final: publish the bottom-edge cotangents to the
+    // strip below and add dL/d(dx) to the path's gradient scratch
+    __device__ void flush_cols(int c0, int c1) {
+        const int CH = chunk_cols(P);
+        const int lane = lane_id();
+        __syncthreads();
+        const int nc = c1 - c0;
+        if (has_below) {
+            double* dst = lam_row + (int64_t)c0 * P;
+            for (int e = lane; e < nc * P; e += kWave) dst[e] = L.lout[e];
+            publish(&lam_prog[s], m - c0);
+        }
+        if (lane < nc) {
+            const int col = c0 + lane;
+            const int sl = ring_slot<P>(col);
+            double* gp = b.gdx + pd->x_off + (int64_t)col * a.d;
+#pragma unroll
+            for (int ch = 0; ch < D; ++ch) {
+                if (ch < a.d) atomicAdd(&gp[ch], L.gx[ch * ring_cols(P) + sl]);
+                L.gx[ch * ring_cols(P) + sl] = 0.0;
+            }
+        }
+        (void)CH;
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ int depth_at(int t) const {
+        const int CH = chunk_cols(P);
+        const int k = min(t, m - 1) / CH;
+        return uniform((int)ckq[k]);
+    }
+
+    __device__ bool sweep() {
+        const int lane = lane_id();
+        const int CH = chunk_cols(P);
+        const int W = kCkptEvery;
+        m = g.m;
+        const int row0 = s * kWave;
+        nrows = min(kWave, g.n - row0);
+        lane_ok = lane < nrows;
+        has_below = s > 0;
+        has_above = row0 + kWave < g.n;
+        R.init();
+        const int l = row0 + lane;
+#pragma unroll
+        for (int ch = 0; ch < D; ++ch) {
+            dy[ch] = (ch < a.d && lane_ok)
+                         ? g.y[(int64_t)(l + 1) * a.d + ch] - g.y[(int64_t)l * a.d + ch]
+                         : 0.0;
+            gy[ch] = 0.0;
+        }
+        for (int e = lane; e < D * ring_cols(P); e += kWave) {
+            L.gx[e] = 0.0;
+            L.dx[e] = 0.0;
+        }
+        const int top = CH * ((m + CH - 1) / CH);
+        dx_lo = kCkptEvery * ((m + kCkptEvery - 1) / kCkptEvery);
+        lin_lo = top;
+        bin_chunk = -1;
+        __syncthreads();
+
+        const int T = m + nrows - 1;
+        double lAprev[P], lBst[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            lAprev[i] = 0.0;
+            lBst[i] = 0.0;
+        }
+        const int topl = has_above ? kWave - 1 : nrows - 1;
+        for (int t0 = ((T - 1) / W) * W; t0 >= 0; t0 -= W) {
+            const int t1 = min(t0 + W, T);
+            const int q = depth_at(t0);
+            load_dx_down_to(max(t0 - (kWave - 1), 0));
+            if (has_above && !load_lin_down_to(max(t0 - (kWave - 1), 0))) return false;
+            if (t0 < m && t0 / CH != bin_chunk) load_bin(t0 / CH);
+            // ---- recompute the segment forward, keeping each step's inputs
+            double B[P], Ac[P];
+            {
+                const double* src = ck + (int64_t)(t0 / W) * (2 * P * kWave);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    B[i] = src[i * kWave + lane];
+                    Ac[i] = src[(P + i) * kWave + lane];
+                }
+            }
+            for (int t = t0; t < t1; ++t) {
+                const int col = t - lane;
+                double A[P];
+                const double* bsrc = &L.bin[(t % CH) * P];
+#pragma unroll
+                for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
+                if (col == 0) {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+                }
+                double* dst = scratch + (int64_t)(t - t0) * (2 * P * kWave);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    dst[i * kWave + lane] = A[i];
+                    dst[(P + i) * kWave + lane] = B[i];
+                }
+                const int ri = ring_slot<P>(col);
+                double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                for (int ch = 0; ch < D; ch += 2) {
+                    c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
+                    c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+                }
+                double An[P], Bn[P];
+                cell_map<P>(A, B, c0 + c1, An, Bn, q, R);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    B[i] = Bn[i];
+                    Ac[i] = An[i];
+                }
+            }
+            // ---- adjoint over the segment, last step first
+            for (int t = t1 - 1; t >= t0; --t) {
+                const int col = t - lane;
+                const bool act = lane_ok && col >= 0 && col < m;
+                const double* src = scratch + (int64_t)(t - t0) * (2 * P * kWave);
+                double A[P], B[P];
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    A[i] = src[i * kWave + lane];
+                    B[i] = src[(P + i) * kWave + lane];
+                }
+                const int ri = ring_slot<P>(col);
+                double dxv[D];
+                double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                for (int ch = 0; ch < D; ch += 2) {
+                    dxv[ch] = L.dx[ch * ring_cols(P) + ri];
+                    dxv[ch + 1] = L.dx[(ch + 1) * ring_cols(P) + ri];
+                    c0 = fma(dy[ch], dxv[ch], c0);
+                    c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
+                }
+                const double c = c0 + c1;
+                // cotangent of the top edge: from the lane above, the strip above
+                // (top lane of a full strip) or the seed of the corner cell
+                const int tcol = t - topl;  // column of the top lane at this step
+                double lAo[P];
+                if (has_above) {
+                    const double* lsrc =
+                        &L.lin[(((tcol >= 0 ? tcol : 0) / CH) & 1) * CH * P +
+                               ((tcol >= 0 ? tcol : 0) % CH) * P];
+#pragma unroll
+                    for (int i = 0; i < P; ++i) lAo[i] = shift_down(lAprev[i], lsrc[i]);
+                } else {
+                    const bool corner = col == m - 1;
+                    double f = seed_scale;
+#pragma unroll
+                    for (int i = 0; i < P; ++i) {
+                        const double topv = corner ? f : 0.0;
+                        lAo[i] = shift_down(lAprev[i], topv);
+                        if (nrows < kWave) lAo[i] = lane == topl ? topv : lAo[i];
+                        f = f * R(i + 1);
+                    }
+                }
+                if (col == m - 1) {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) lBst[i] = 0.0;
+                }
+                double lA[P], lB[P];
+                double gc = cell_adjoint<P>(A, B, c, q, lAo, lBst, lA, lB, R);
+                if (!act) gc = 0.0;
+#pragma unroll
+                for (int ch = 0; ch < D; ++ch) gy[ch] = fma(gc, dxv[ch], gy[ch]);
+                if (act) {
+#pragma unroll
+                    for (int ch = 0; ch < D; ++ch) {
+                        double& gv = L.gx[ch * ring_cols(P) + ri];
+                        gv = fma(gc, dy[ch], gv);
+                    }
+                    if (lane == 0) {
+#pragma unroll
+                        for (int i = 0; i < P; ++i) L.lout[(col % CH) * P + i] = lA[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    lBst[i] = lB[i];
+                    lAprev[i] = lA[i];
+                }
+            }
+            if (t0 < m && (t0 % CH) == 0) flush_cols(t0, min(t0 + CH, m));
+        }
+        // dL/d(dy_l) of this lane's row
+        if (lane_ok) {
+            double* gp = b.gdx + pd->y_off + (int64_t)l * a.d;
+#pragma unroll
+            for (int ch = 0; ch < D; ++ch)
+                if (ch < a.d) atomicAdd(&gp[ch], gy[ch]);
+        }
+        __syncthreads();
+        return true;
+    }
+};
+
+template <int P, int D>
+__global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
+    __shared__ LdsBwd<P, D> L;
+    const FwdArgs& a = b.f;
+    const int lane = lane_id();
+    double* scratch = b.scratch + (int64_t)blockIdx.x * (kCkptEvery * 2 * P * kWave);
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&a.hdr->ticket2, 1u);
+        t = (unsigned)uniform((int)t);
+        if ((int64_t)t >= b.ntickets) break;
+        if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
+        const int pair = b.tickets[t].pair, strip = b.tickets[t].strip;
+        Geo g = resolve(a, pair, P, 0);
+        const PairDesc& pd = a.desc[pair];
+        StripBwd<P, D> S(b, g, L, strip);
+        S.pd = &pd;
+        S.scratch = scratch;
+        S.ck = b.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
+        S.ckq = S.ck + ckpt_states(g.m) * 2 * P * kWave;
+        S.snap_in = b.snap + pd.snap_off + (int64_t)strip * g.m * P;
+        S.lam_row = b.lam_front + pd.front_off;
+        S.lam_prog = b.lam_prog + pd.prog_off;
+        S.seed_scale = b.grad_out[pair];
+        if (!S.sweep()) break;
+    }
+}
+
 #define SIGK_CAT3(a, b, c) a##b##_##c
 #define SIGK_NAME(pre, P, D) SIGK_CAT3(pre, P, D)
-hipError_t SIGK_NAME(launch_ckpt_, SIGK_P, SIGK_D)(const FwdArgs&, int, hipStream_t) {
-    return hipErrorNotSupported;
+
+hipError_t SIGK_NAME(launch_ckpt_, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((ckpt_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, a,
+                       a.frontier);
+    return hipGetLastError();
 }
-hipError_t SIGK_NAME(launch_bwd_, SIGK_P, SIGK_D)(const BwdArgs&, int, hipStream_t) {
-    return hipErrorNotSupported;
+
+hipError_t SIGK_NAME(launch_bwd_, SIGK_P, SIGK_D)(const BwdArgs& b, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((bwd_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, b);
+    return hipGetLastError();
 }
-int SIGK_NAME(occupancy_bwd_, SIGK_P, SIGK_D)() { return 1; }
+
+int SIGK_NAME(occupancy_bwd_, SIGK_P, SIGK_D)() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bwd_kernel<SIGK_P, SIGK_D>, kWave, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
 }  // namespace sigk

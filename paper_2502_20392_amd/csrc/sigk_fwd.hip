@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(kWave) fwd_kernel(FwdArgs a) {
         S.Fin = S.Fout;
         S.prog = a.progress + g.prog;
         S.ck = nullptr;
+        S.ckq = nullptr;
         S.ck_every = 1;
         if (!S.sweep()) break;
     }

@@ -32,14 +32,28 @@ __host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }
 struct PairDesc {
     int64_t x_off;      // first double of path x in the pool
     int64_t y_off;      // first double of path y in the pool
-    int64_t front_off;  // first double of this pair's frontier / checkpoint area
+    int64_t front_off;  // first double of this pair's frontier row ([m][P])
     int64_t ckpt_off;   // first double of this pair's adjoint checkpoints
+    int64_t snap_off;   // first double of this pair's frontier snapshots ([S][m][P])
     int32_t lx, ly;     // points
     int32_t prog_off;   // first progress counter (one per strip)
     int32_t out_idx;    // output slot
     int32_t out_idx2;   // mirror output slot or -1
     int32_t pad;
 };
+static_assert(sizeof(PairDesc) == 64, "descriptor size");
+
+// Adjoint checkpointing: wave state every kCkptEvery steps; per strip
+// ckpt_states(m) states of 2P x 64 doubles followed by the Neumann depth of
+// every frontier chunk (stored as doubles, padded to 64).
+constexpr int kCkptEvery = 16;
+__host__ __device__ constexpr int64_t ckpt_states(int64_t m) {
+    return (m + kWave + kCkptEvery - 1) / kCkptEvery + 1;
+}
+__host__ __device__ constexpr int64_t ckpt_strip_doubles(int64_t m, int P) {
+    return ckpt_states(m) * 2 * P * kWave +
+           ((m + chunk_cols(P) - 1) / chunk_cols(P) + kWave - 1) / kWave * kWave;
+}
 
 struct Ticket {
     int32_t pair;
@@ -85,12 +99,16 @@ struct FwdArgs {
 };
 
 struct BwdArgs {
-    FwdArgs f;               // geometry, thresholds, checkpoints
-    const double* grad_out;  // [npairs]
-    double* gpool;           // [sum len][d] accumulated gradient
-    double* lam_front;       // adjoint frontier (one per pair, [m][P])
-    int* lam_prog;           // adjoint progress counters
-    double* gdx;             // [sum len][d] scratch: gradient w.r.t. increments
+    FwdArgs f;               // geometry (table mode), depth thresholds
+    const Ticket* tickets;   // adjoint order (top strip of each pair first)
+    int64_t ntickets;
+    const double* grad_out;  // [npairs] weights of the kernel values
+    double* snap;            // frontier snapshots written by the checkpoint pass
+    double* ckpt;            // wave-state checkpoints + per-chunk depths
+    double* lam_front;       // adjoint frontier (one row per pair, [m][P])
+    int* lam_prog;           // adjoint progress counters (columns done from the right)
+    double* gdx;             // [sum len][d]: dL/d(increment) at the increment's first point
+    double* scratch;         // per workgroup: kCkptEvery x 2P x 64 recomputed cell inputs
 };
 
 // Launchers implemented per variant (one translation unit each).

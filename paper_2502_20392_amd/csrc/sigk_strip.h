@@ -182,6 +182,7 @@ struct StripCtx {
     Recip<P> R;
     // checkpointing (adjoint support)
     double* ck;         // wave-state checkpoints of this strip or null
+    double* ckq;        // Neumann depth per chunk (with ck)
     int ck_every;
 
     __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D>& L_, Acc& acc_, int s_)
@@ -221,6 +222,7 @@ struct StripCtx {
 #pragma unroll
         for (int n = 1; n < P; ++n) qq = cmax2 > a.tau2[n] ? n : qq;
         q = uniform(qq);
+        if (ckq && lane == 0) ckq[c0 / CH] = (double)q;
         return true;
     }
 
@@ -390,7 +392,7 @@ struct StripCtx {
             // the last row's lane holds the top edge of the corner cell
             const bool mine = lane == nrows - 1;
             tail_check<P>(Ac, a.tail_tol, mine, acc.status);
-            if (mine) {
+            if (mine && a.out) {
                 double k = 0.0, f = 1.0;
 #pragma unroll
                 for (int i = 0; i < P; ++i) {

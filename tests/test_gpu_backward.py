@@ -1,0 +1,153 @@
+"""GPU parity of the adjoint (gradient) path against the oracle's continuous adjoint,
+closed forms, identities and central finite differences."""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def sk():
+    import paper_2502_20392_amd as P
+    return P
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def gpu_pair_grad(x, y, dev, order=12, w=1.0):
+    pool = np.concatenate([x, y])
+    off = np.array([0, len(x), len(x) + len(y)], dtype=np.int64)
+    plan = sk().RaggedPlan(off, np.array([[0, 1]], dtype=np.int32), x.shape[1], order=order,
+                           device=dev)
+    pd = T(pool, dev)
+    k = plan.run(pd).item()
+    g = plan.backward(pd, torch.tensor([w], dtype=torch.float64, device=dev)).cpu().numpy()
+    return k, g[: len(x)], g[len(x):]
+
+
+@pytest.mark.parametrize("lx,ly", [(2, 2), (5, 7), (70, 66), (130, 129), (20, 150), (150, 20),
+                                   (65, 64)])
+def test_pair_gradient_vs_oracle(dev, lx, ly):
+    g = synth.rng(4000 + lx + 3 * ly)
+    x = np.cumsum(g.normal(size=(lx, 3)) * 0.2, axis=0)
+    y = np.cumsum(g.normal(size=(ly, 3)) * 0.2, axis=0)
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=16)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-12 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-10 * sc
+    assert np.abs(gy - gy0).max() <= 1e-10 * sc
+    assert sk().counters()["status"] == 0
+
+
+def test_weighted_batch_shared_paths(dev):
+    """Several pairs sharing paths, weighted: gradient is sum_p w_p grad k_p."""
+    pool, off, _ = synth.ragged_paths(n_paths=5, lmin=20, lmax=90, d=4, smin=0.3, smax=0.6)
+    pairs = np.array([[0, 1], [1, 2], [2, 2], [3, 0], [4, 1], [0, 0]], dtype=np.int32)
+    w = np.array([0.5, -1.0, 2.0, 0.25, 1.5, -0.75])
+    ref = np.zeros_like(pool)
+    for (a, b), wi in zip(pairs, w):
+        xa, xb = pool[off[a]:off[a + 1]], pool[off[b]:off[b + 1]]
+        _, ga, gb = oracle.grad(xa, xb)
+        ref[off[a]:off[a + 1]] += wi * ga
+        ref[off[b]:off[b + 1]] += wi * gb
+    plan = sk().RaggedPlan(off, pairs, 4, order=16, device=dev)
+    pd = T(pool, dev)
+    plan.run(pd)
+    gp = plan.backward(pd, T(w, dev)).cpu().numpy()
+    assert np.abs(gp - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_d1_closed_form_gradient(dev):
+    g = synth.rng(4100)
+    x = np.cumsum(g.normal(size=(300, 1)) * 0.05, axis=0)
+    y = np.cumsum(g.normal(size=(250, 1)) * 0.05, axis=0)
+    X = x[-1, 0] - x[0, 0]
+    Y = y[-1, 0] - y[0, 0]
+    p = X * Y
+    dkdX = Y * (sp.i1(2 * math.sqrt(p)) / math.sqrt(p) if p > 0 else
+                sp.j1(2 * math.sqrt(-p)) / math.sqrt(-p))
+    _, gx, _ = gpu_pair_grad(x, y, dev, order=10)
+    assert abs(gx[-1, 0] - dkdX) < 1e-11 * max(1, abs(dkdX))
+    assert abs(gx[0, 0] + dkdX) < 1e-11 * max(1, abs(dkdX))
+    assert np.abs(gx[1:-1, 0]).max() < 1e-11 * max(1, abs(dkdX))
+
+
+def test_autograd_gram(dev):
+    X = synth.brownian(4, 40, 3, 0.8, seed=41)
+    Wt = synth.rng(42).normal(size=(4, 4))
+    Xt = T(X, dev).requires_grad_(True)
+    G = sk().sigkernel_gram(Xt, order=12)
+    (G * T(Wt, dev)).sum().backward()
+    ref = np.zeros_like(X)
+    for i in range(4):
+        for j in range(4):
+            _, gi, gj = oracle.grad(X[i], X[j])
+            ref[i] += Wt[i, j] * gi
+            ref[j] += Wt[i, j] * gj
+    np.testing.assert_allclose(G.detach().cpu().numpy(), oracle.gram(X), rtol=1e-12, atol=1e-12)
+    assert np.abs(Xt.grad.cpu().numpy() - ref).max() <= 1e-10 * max(1, np.abs(ref).max())
+
+
+def mmd2_oracle(X, Y):
+    nx, ny = len(X), len(Y)
+    kxx = sum(oracle.pair(X[i], X[j]) for i in range(nx) for j in range(nx)) / nx ** 2
+    kyy = sum(oracle.pair(Y[i], Y[j]) for i in range(ny) for j in range(ny)) / ny ** 2
+    kxy = sum(oracle.pair(X[i], Y[j]) for i in range(nx) for j in range(ny)) / (nx * ny)
+    return kxx + kyy - 2 * kxy
+
+
+def test_mmd_reduced_vs_oracle(dev):
+    """MMD^2 and dMMD^2/dX on a reduced copy of the MMD workload (4 + 4 paths, length 256)."""
+    X, Y = synth.mmd_sets(n=4, length=256)
+    Xt = T(X, dev).requires_grad_(True)
+    Yt = T(Y, dev)
+    m = sk().mmd2(Xt, Yt, order=10)
+    m.backward()
+    nx, ny = 4, 4
+    ref = np.zeros_like(X)
+    for i in range(nx):
+        for j in range(nx):
+            _, gi, gj = oracle.grad(X[i], X[j])
+            ref[i] += gi / nx ** 2
+            ref[j] += gj / nx ** 2
+        for j in range(ny):
+            _, gi, _ = oracle.grad(X[i], Y[j])
+            ref[i] += -2 * gi / (nx * ny)
+    assert abs(m.item() - mmd2_oracle(X, Y)) <= 1e-12
+    assert np.abs(Xt.grad.cpu().numpy() - ref).max() <= 1e-10 * max(1, np.abs(ref).max())
+
+
+def test_mmd_full_size_finite_differences(dev):
+    """Full MMD workload (32 + 32 paths, length 2048, d 8): autograd gradient vs
+    central differences (h = 1e-6) on sampled coordinates."""
+    X, Y = synth.mmd_sets()
+    Xt = T(X, dev).requires_grad_(True)
+    Yt = T(Y, dev)
+    m = sk().mmd2(Xt, Yt, order=10)
+    m.backward()
+    grad = Xt.grad.cpu().numpy()
+    g = synth.rng(43)
+    h = 1e-6
+    coords = [(int(g.integers(32)), int(g.integers(2048)), int(g.integers(8))) for _ in range(6)]
+    coords += [(0, 0, 0), (5, 2047, 7)]
+    for c in coords:
+        Xp = X.copy()
+        Xp[c] += h
+        Xm = X.copy()
+        Xm[c] -= h
+        fp = sk().mmd2(T(Xp, dev), Yt, order=10).item()
+        fm = sk().mmd2(T(Xm, dev), Yt, order=10).item()
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - grad[c]) <= 1e-6 * max(1e-3, abs(grad).max()), (c, fd, grad[c])
+    # translation invariance: gradients over the points of each path sum to zero
+    assert np.abs(grad.sum(axis=1)).max() <= 1e-10 * max(1, np.abs(grad).max())
