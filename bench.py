@@ -1,17 +1,23 @@
 """Benchmark: Goursat grid cells/s of the signature-kernel solver on one MI355X.
 
-Workload (default): one pair of fractional Brownian paths, 1,000,000 points each,
-d = 8, Hurst 0.2 (Davies-Harte), each channel scaled to quadratic variation 1;
-k(x, y) in FP64 by libsigk.  One "step" = one full evaluation of k(x, y)
-(increments, cell coefficients, truncated cell maps with adaptive Neumann depth,
-wavefront propagation over the 999,999 x 999,999 grid, corner value).
+Headline workload: one pair of fractional Brownian paths, 1,000,000 points each,
+d = 8, Hurst 0.2 (Davies-Harte), every channel scaled to quadratic variation 1;
+k(x, y) in FP64 by libsigk.  One step = one full evaluation of k(x, y):
+increments, cell coefficients, truncated cell maps with adaptive Neumann
+depth, wavefront propagation over the 999,999 x 999,999 grid, corner value.
 
-Prints one JSON line (see the contract in the design notes): value = cells/s,
-plus a roofline object for the forward kernel (algorithmic FP64 flops per
-launch, counted on the device, over the kernel's event-timed duration, against
-the MI355X FP64 vector peak) and the CPU oracle timed on a bounded sample.
+Also measured (field "workloads"): the 64 x 64 Gram (length 1024, d 16,
+sigma 1 and 4), the ragged batch of 512 pairs (graph replay, autotuned order),
+MMD^2 forward + backward (32 + 32 paths, length 2048, d 8) and the 8 x 8 Gram.
+
+Prints ONE JSON line.  "roofline" covers the forward kernel of the headline
+workload: algorithmic FP64 flops per launch (counted on the device: the
+truncated cell maps actually applied, FMA = 2) over its HIP-event time on the
+launch stream, against the MI355X FP64 vector peak.  "cpu_baseline" is the
+CPU oracle timed on a bounded prefix of the same pair.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+HEADLINE_ORDER = 6
+METRIC = "Goursat grid cells/s (fwd, fwd+bwd) at rel err ≤1e-10 vs FP64 oracle"
 
 
 def parse():
@@ -31,12 +39,108 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--length", type=int, default=1_000_000)
-    ap.add_argument("--order", type=int, default=5)
-    ap.add_argument("--tol", type=float, default=0.0)
-    ap.add_argument("--cpu-sample", type=int, default=6001,
+    ap.add_argument("--order", type=int, default=HEADLINE_ORDER)
+    ap.add_argument("--cpu-sample", type=int, default=7001,
                     help="points of the prefix pair the CPU oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2502_20392_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(order):
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, if it was taken on the current kernel sources and order."""
+    path = os.path.join(ROOT, "profiles", "fwd_kernel_long_pair_traffic.json")
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("kernel_source_digest") != kernel_source_digest() or t.get("order") != order:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def timed(fn, torch, steps=3):
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def extras(torch, sk, dev):
+    import synth
+    import paper_2502_20392_amd.tune as tune
+    res = {}
+
+    def frac(flops, ms):
+        return flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS
+
+    for name, sig, order in (("gram64_len1024_d16_sigma1", 1.0, 12),
+                             ("gram64_len1024_d16_sigma4", 4.0, 20)):
+        X = torch.from_numpy(synth.gram_mid(sig)).to(dev)
+        ms = timed(lambda: sk.gram(X, order=order), torch)
+        c = sk.counters()
+        res[name] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": order,
+                     "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+    X = torch.from_numpy(synth.gram_small()).to(dev)
+    ms = timed(lambda: sk.gram(X, order=12), torch)
+    c = sk.counters()
+    res["gram8_len128_d3"] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": 12,
+                              "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+    # ragged batch: autotuned order and grid, one persistent launch in a HIP graph
+    pool, off, pairs = synth.ragged_paths()
+    pd = torch.from_numpy(pool).to(dev)
+    tuned = tune.tune_ragged(pd, off, pairs, hint=16, use_cache=False)
+    plan = sk.RaggedPlan(off, pairs, pool.shape[1], order=tuned["order"], grid=tuned["grid"],
+                         device=dev)
+    out = torch.empty(plan.npairs, dtype=torch.float64, device=dev)
+    g = plan.capture(pd, out)
+    ms = timed(g.replay, torch)
+    c = sk.counters(plan.ws)
+    res["ragged512_len64to4096_d32_graph"] = {
+        "cells_per_s": plan.cells / (ms / 1e3), "ms": ms, "order": tuned["order"],
+        "grid": tuned["grid"], "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+    # MMD^2 forward + backward (gradient with respect to X)
+    Xm, Ym = synth.mmd_sets()
+    Xt = torch.from_numpy(Xm).to(dev).requires_grad_(True)
+    Yt = torch.from_numpy(Ym).to(dev)
+
+    def fb():
+        Xt.grad = None
+        sk.mmd2(Xt, Yt, order=10).backward()
+
+    ms = timed(fb, torch, steps=2)
+    nx, lx = Xm.shape[0], Xm.shape[1]
+    ny, ly = Ym.shape[0], Ym.shape[1]
+    fwd_cells = (nx * (nx + 1) // 2 * (lx - 1) ** 2 + ny * (ny + 1) // 2 * (ly - 1) ** 2
+                 + nx * ny * (lx - 1) * (ly - 1))
+    bwd_cells = nx * (nx + 1) // 2 * (lx - 1) ** 2 + nx * ny * (lx - 1) * (ly - 1)
+    res["mmd_32x32_len2048_d8_fwd_bwd"] = {
+        "cells_per_s": fwd_cells / (ms / 1e3), "ms": ms, "order": 10,
+        "fwd_cells": fwd_cells, "bwd_cells": bwd_cells,
+        "note": "fwd+bwd: forward cells over the time of forward plus backward"}
+    return res
 
 
 def main():
@@ -50,26 +154,26 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8}))
+        return
     t0 = time.time()
     x, y = synth.long_pair(length=args.length)
-    gen_s = time.time() - t0
     xd = torch.from_numpy(x).to(dev)
     yd = torch.from_numpy(y).to(dev)
-    d = x.shape[1]
     cells = (x.shape[0] - 1) * (y.shape[0] - 1)
-    tol = args.tol if args.tol > 0 else None
-    ws = None
-    print(f"# workload ready ({gen_s:.1f}s): pair {x.shape} x {y.shape}, cells {cells:.3e}",
-          file=sys.stderr, flush=True)
-
-    def step():
-        return sk.pair(xd, yd, order=args.order, tol=tol, ws=ws)
-
-    k = step()
+    print(f"# workload ready ({time.time() - t0:.1f}s): pair {x.shape} x {y.shape}, "
+          f"cells {cells:.3e}", file=sys.stderr, flush=True)
+    k = sk.pair(xd, yd, order=args.order)
     ws = sk.last_workspace()
-    torch.cuda.synchronize()
     for _ in range(max(args.warmup - 1, 0)):
-        step()
+        sk.pair(xd, yd, order=args.order, ws=ws)
     torch.cuda.synchronize()
     cnt = sk.counters(ws)
     print(f"# warmup done: k = {k.item():.17g}, status {cnt['status']}", file=sys.stderr,
@@ -79,10 +183,11 @@ def main():
            for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    for e0, e1 in evs:
+    for i, (e0, e1) in enumerate(evs):
         e0.record(s)
-        step()
+        kk = sk.pair(xd, yd, order=args.order, ws=ws)
         e1.record(s)
+        print(f"# step {i} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     kernel_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
@@ -90,8 +195,9 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     avg_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = cnt["flops"] / avg_kernel_s / 1e12
+    traffic = traffic_from_profile(cnt["order"])
     out = {
-        "metric": "Goursat grid cells/s (fwd, fwd+bwd) at rel err <=1e-10 vs FP64 oracle",
+        "metric": METRIC,
         "value": cells / (ms_per_step / 1e3),
         "unit": "cells/s",
         "n_gpus": 1,
@@ -103,18 +209,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single pair, 1e6 points each, d=8, fBM H=0.2 (Davies-Harte), "
-                               "quadratic variation 1 per channel, forward",
-                   "length": args.length, "d": d, "order": cnt["order"],
-                   "tol": tol or 2.0 ** -53, "cells_per_step": cells},
-        "k": k.item(),
+        "config": {"workload": "single pair k(x, y), 1e6 points each, d=8, fBM H=0.2 "
+                               "(Davies-Harte, seed 4), quadratic variation 1 per channel, "
+                               "forward",
+                   "length": args.length, "d": int(x.shape[1]), "order": cnt["order"],
+                   "tol": 2.0 ** -53, "cells_per_step": cells},
+        "k": kk.item(),
         "status": cnt["status"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "fwd_kernel", "flops_per_launch": cnt["flops"],
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": f"fwd_kernel<{cnt['order']}, 8>",
+                     "flops_per_launch": cnt["flops"],
+                     "flops_per_cell": cnt["flops"] / max(cnt["cells"], 1),
                      "kernel_ms": float(np.mean(kernel_ms))},
-        "peak_mem_bytes": torch.cuda.max_memory_allocated(dev),
+        "peak_mem_bytes": int(torch.cuda.max_memory_allocated(dev)),
+        "kernel_source_digest": kernel_source_digest(),
     }
+    if not args.no_extras:
+        print("# extra workloads", file=sys.stderr, flush=True)
+        out["workloads"] = extras(torch, sk, dev)
     if not args.no_cpu:
         import oracle
         n = args.cpu_sample
@@ -124,12 +237,12 @@ def main():
         cs = time.perf_counter() - c0
         scells = (n - 1) ** 2
         kg = sk.pair(torch.from_numpy(xs).to(dev), torch.from_numpy(ys).to(dev),
-                     order=args.order, tol=tol).item()
+                     order=args.order).item()
         out["cpu_baseline"] = {"value": scells / cs, "unit": "cells/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"prefix pair {n}x{n} points of the same workload "
-                                         f"({scells:.3e} cells, {cs:.1f}s, one thread: the "
-                                         f"raster sweep of one pair is sequential)"}
+                                         f"({scells:.3e} cells, {cs:.1f} s); one thread: the "
+                                         f"raster sweep of one pair is sequential"}
         out["parity_sample"] = {"sample": f"prefix {n}x{n}", "gpu": kg, "oracle": kref,
                                 "rel_err": abs(kg - kref) / max(abs(kref), 1.0)}
     print(json.dumps(out))

@@ -176,6 +176,9 @@ int sigk_read_status(const void* ws, uint32_t* status_bits, void* stream);
 const char* sigk_strerror(int code);
 /* Compiled edge orders and dimension buckets (host). */
 int sigk_supported_order(int order); /* smallest compiled P >= order, or 0 */
+/* Persistent workgroups that fill the current device for this variant (host;
+   queries the HIP runtime, no device work).  0 if the variant does not exist. */
+int sigk_device_grid(int order, int64_t d, int backward);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,7 @@ _SZ = ctypes.c_size_t
 SIGNATURES = {
     "sigk_default_opts": (None, [ctypes.POINTER(Opts)]),
     "sigk_supported_order": (ctypes.c_int, [ctypes.c_int]),
+    "sigk_device_grid": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int]),
     "sigk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sigk_pair_workspace_size": (ctypes.c_int, [_I64, _I64, _I64, ctypes.POINTER(Opts),
                                                 ctypes.POINTER(_SZ)]),

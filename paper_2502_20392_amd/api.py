@@ -191,6 +191,18 @@ class RaggedPlan:
         _tls.ws = ws
         return out
 
+    def capture(self, pool, out):
+        """Record ``run(pool, out)`` (reset kernel + persistent launch) into a HIP graph.
+
+        The workspace, the tables and the occupancy query are prepared by an
+        eager run first; the graph then replays with whatever ``pool`` holds."""
+        self.run(pool, out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(pool, out)
+        return g
+
     def backward(self, pool, grad_out, grad_pool=None):
         """grad_pool += d(sum_p grad_out[p] k_p)/d pool."""
         pool = _check_paths(pool, "pool", 2)
@@ -288,7 +300,10 @@ def sigkernel_gram(X, Y=None, order=12, tol=None):
 
 
 class _MMD2Function(torch.autograd.Function):
-    """Biased MMD^2 = mean k(X,X) + mean k(Y,Y) - 2 mean k(X,Y) in one ragged launch."""
+    """Biased MMD^2 = mean k(X,X) + mean k(Y,Y) - 2 mean k(X,Y) in one ragged launch.
+
+    The backward runs the adjoint only over the pairs that involve an input
+    that needs a gradient (XX and XY for dMMD^2/dX)."""
 
     @staticmethod
     def forward(ctx, X, Y, order, tol):
@@ -300,23 +315,34 @@ class _MMD2Function(torch.autograd.Function):
         xi, xj = np.triu_indices(nx)
         yi, yj = np.triu_indices(ny)
         ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
-        pairs = np.concatenate([np.stack([xi, xj], 1), np.stack([nx + yi, nx + yj], 1),
-                                np.stack([ci.ravel(), nx + cj.ravel()], 1)]).astype(np.int32)
-        w = np.concatenate([np.where(xi == xj, 1.0, 2.0) / (nx * nx),
-                            np.where(yi == yj, 1.0, 2.0) / (ny * ny),
-                            np.full(nx * ny, -2.0 / (nx * ny))])
+        blocks = [np.stack([xi, xj], 1), np.stack([nx + yi, nx + yj], 1),
+                  np.stack([ci.ravel(), nx + cj.ravel()], 1)]
+        weights = [np.where(xi == xj, 1.0, 2.0) / (nx * nx),
+                   np.where(yi == yj, 1.0, 2.0) / (ny * ny),
+                   np.full(nx * ny, -2.0 / (nx * ny))]
+        pairs = np.concatenate(blocks).astype(np.int32)
         plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
         vals = plan.run(pool)
-        wt = torch.from_numpy(w).to(X.device)
-        ctx.plan, ctx.pool, ctx.wt, ctx.shapes = plan, pool, wt, (X.shape, Y.shape)
+        wt = torch.from_numpy(np.concatenate(weights)).to(X.device)
+        ctx.save = (offsets, blocks, weights, d, order, tol)
+        ctx.pool, ctx.shapes = pool, (X.shape, Y.shape)
         return (vals * wt).sum()
 
     @staticmethod
     def backward(ctx, g):
-        gpool = ctx.plan.backward(ctx.pool, (ctx.wt * g).contiguous())
+        offsets, blocks, weights, d, order, tol = ctx.save
+        need_x, need_y = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        use = [need_x, need_y, need_x or need_y]  # XX, YY, XY blocks
+        pairs = np.concatenate([b for b, u in zip(blocks, use) if u]).astype(np.int32)
+        w = np.concatenate([x for x, u in zip(weights, use) if u])
+        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=ctx.pool.device)
+        wt = torch.from_numpy(w).to(ctx.pool.device) * g
+        gpool = plan.backward(ctx.pool, wt.contiguous())
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
-        return gpool[:nxp].reshape(xs), gpool[nxp:].reshape(ys), None, None
+        gx = gpool[:nxp].reshape(xs) if need_x else None
+        gy = gpool[nxp:].reshape(ys) if need_y else None
+        return gx, gy, None, None
 
 
 def mmd2(X, Y, order=12, tol=None):

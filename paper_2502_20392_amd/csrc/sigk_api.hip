@@ -246,6 +246,14 @@ void sigk_default_opts(sigk_opts* o) {
 
 int sigk_supported_order(int order) { return round_order(order); }
 
+int sigk_device_grid(int order, int64_t d, int backward) {
+    const int P = round_order(order);
+    const int D = round_dim(d);
+    if (!P || !D) return 0;
+    if (backward && !find_bwd(P, D)) return 0;
+    return device_wgs(P, D, backward != 0);
+}
+
 const char* sigk_strerror(int code) {
     switch (code) {
         case SIGK_OK: return "ok";

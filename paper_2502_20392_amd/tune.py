@@ -1,0 +1,135 @@
+"""Autotuner for libsigk launches: edge order P (the truncation budget) and the
+persistent grid, per workload, with a JSON cache.
+
+Order: the smallest compiled P, from a starting hint upwards, whose run raises
+no truncation warning on the device (the last kept edge coefficient weighs at
+most tail_tol of the edge norm everywhere the kernel samples it).  Grid: the
+fastest of a few fractions of the device-filling grid, timed with HIP events.
+Results are cached under a key built from the workload's shape and a digest of
+its data, in $SIGK_TUNE_CACHE (default ~/.cache/sigk_tune.json).
+"""
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib
+from .api import RaggedPlan, counters, pair
+
+_DEF_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sigk_tune.json")
+
+
+def _cache_path():
+    return os.environ.get("SIGK_TUNE_CACHE", _DEF_CACHE)
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except Exception:
+        return {}
+
+
+def _store(key, val):
+    c = _load_cache()
+    c[key] = val
+    path = _cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1)
+    os.replace(tmp, path)
+
+
+def _digest(*arrays):
+    h = hashlib.sha1()
+    for a in arrays:
+        if isinstance(a, torch.Tensor):
+            a = a.detach().cpu().numpy()
+        a = np.ascontiguousarray(a)
+        h.update(str(a.shape).encode())
+        h.update(a.tobytes()[: 1 << 22])
+    return h.hexdigest()[:16]
+
+
+def _time(fn, reps):
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def _grid_candidates(order, d):
+    full = _lib.load().sigk_device_grid(int(order), int(d), 0)
+    if full <= 0:
+        return [0]
+    return [0] + sorted({max(1, full // 2), max(1, (3 * full) // 4)})
+
+
+def tune_ragged(pool, offsets, pairs, hint=6, reps=2, tol=None, use_cache=True):
+    """Tune a ragged batch.  Returns {"order", "grid", "ms", "status"}."""
+    d = pool.shape[1]
+    key = "ragged:" + _digest(offsets, pairs, pool) + f":{hint}:{tol}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            return hit
+    ladder = [p for p in _lib.ORDERS if p >= hint] or [_lib.ORDERS[-1]]
+    order, status = ladder[-1], None
+    for p in ladder:
+        plan = RaggedPlan(offsets, pairs, d, order=p, tol=tol, device=pool.device)
+        plan.run(pool)
+        st = counters(plan.ws)["status"]
+        if not st & _lib.WARN_TRUNC:
+            order, status = p, st
+            break
+        status = st
+    best = None
+    for g in _grid_candidates(order, d):
+        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, grid=g, device=pool.device)
+        out = torch.empty(plan.npairs, dtype=torch.float64, device=pool.device)
+        ms = _time(lambda: plan.run(pool, out), reps)
+        if best is None or ms < best["ms"]:
+            best = {"order": order, "grid": g, "ms": ms, "status": status}
+    if use_cache:
+        _store(key, best)
+    return best
+
+
+def tune_pair(x, y, hint=5, reps=1, tol=None, use_cache=True):
+    """Tune one pair evaluation.  Returns {"order", "grid", "ms", "status"}."""
+    key = "pair:" + _digest(x, y) + f":{hint}:{tol}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            return hit
+    ladder = [p for p in _lib.ORDERS if p >= hint] or [_lib.ORDERS[-1]]
+    order, status = ladder[-1], None
+    for p in ladder:
+        pair(x, y, order=p, tol=tol)
+        st = counters()["status"]
+        status = st
+        if not st & _lib.WARN_TRUNC:
+            order = p
+            break
+    best = None
+    for g in _grid_candidates(order, x.shape[1]):
+        ms = _time(lambda: pair(x, y, order=order, tol=tol, grid=g), reps)
+        if best is None or ms < best["ms"]:
+            best = {"order": order, "grid": g, "ms": ms, "status": status}
+    if use_cache:
+        _store(key, best)
+    return best

@@ -1,0 +1,81 @@
+"""Full-size checks of the 1,000,000-point pair (d 8, fBM H 0.2), in the launch
+configuration the benchmark times (order 6, default grid).
+
+The full-size oracle is out of reach (~1e12 cells), so parity uses exact
+identities: subdivision invariance against a stored oracle value (written by
+tests/golden/make_long_pair_golden.py from the oracle only), and the closed
+form of a straight line against any path."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "long_pair_coarse.json")
+ORDER = 6
+
+
+def sk():
+    import paper_2502_20392_amd as P
+    return P
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.fixture(scope="module")
+def long_pair():
+    return synth.long_pair()
+
+
+def subdivide(xc, pieces):
+    f = np.arange(pieces, dtype=np.float64) / pieces
+    seg = xc[:-1, None, :] + f[None, :, None] * (xc[1:] - xc[:-1])[:, None, :]
+    return np.concatenate([seg.reshape(-1, xc.shape[1]), xc[-1:]], axis=0)
+
+
+def test_subdivision_equivalence_full_size(dev, long_pair):
+    """k(x_sub, y) on ~1e12 cells equals the oracle's k(x_coarse, y) on ~1e9 cells."""
+    gold = json.load(open(GOLDEN))
+    x, y = long_pair
+    xc = x[:: gold["stride"]]
+    assert len(xc) == gold["coarse_points"] and len(y) == gold["y_points"]
+    xs = subdivide(xc, gold["stride"])
+    k = sk().pair(T(xs, dev), T(y, dev), order=ORDER).item()
+    c = sk().counters()
+    assert c["status"] == 0
+    assert c["cells"] == (len(xs) - 1) * (len(y) - 1)
+    assert abs(k - gold["k"]) / max(abs(gold["k"]), 1.0) < 1e-10, (k, gold["k"])
+
+
+def test_straight_line_full_size(dev, long_pair):
+    """x a straight segment sampled at 1e6 points: k = I0(2 sqrt(<a, Y>)) (or J0)."""
+    x, y = long_pair
+    a = x[-1] - x[0]
+    t = np.linspace(0.0, 1.0, len(x))
+    xl = t[:, None] * a[None, :]
+    z = float(a @ (y[-1] - y[0]))
+    ref = float(sp.i0(2 * math.sqrt(z))) if z >= 0 else float(sp.j0(2 * math.sqrt(-z)))
+    k = sk().pair(T(xl, dev), T(y, dev), order=ORDER).item()
+    assert abs(k - ref) / max(abs(ref), 1.0) < 1e-10, (k, ref)
+
+
+def test_workload_status_and_symmetry(dev, long_pair):
+    """The benchmark's own evaluation: no truncation warning, finite, and
+    k(x, y) == k(y, x) (different sweep orientation) to 1e-10."""
+    x, y = long_pair
+    xd, yd = T(x, dev), T(y, dev)
+    k1 = sk().pair(xd, yd, order=ORDER).item()
+    assert sk().counters()["status"] == 0
+    k2 = sk().pair(yd, xd, order=ORDER).item()
+    assert math.isfinite(k1) and abs(k1 - k2) / max(abs(k1), 1.0) < 1e-10
