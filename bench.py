@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--length", type=int, default=1_000_000)
     ap.add_argument("--order", type=int, default=HEADLINE_ORDER)
+    ap.add_argument("--tol", type=float, default=0.0, help="Neumann tolerance (0: by size)")
     ap.add_argument("--cpu-sample", type=int, default=7001,
                     help="points of the prefix pair the CPU oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
@@ -170,10 +171,11 @@ def main():
     cells = (x.shape[0] - 1) * (y.shape[0] - 1)
     print(f"# workload ready ({time.time() - t0:.1f}s): pair {x.shape} x {y.shape}, "
           f"cells {cells:.3e}", file=sys.stderr, flush=True)
-    k = sk.pair(xd, yd, order=args.order)
+    tol = args.tol or None
+    k = sk.pair(xd, yd, order=args.order, tol=tol)
     ws = sk.last_workspace()
     for _ in range(max(args.warmup - 1, 0)):
-        sk.pair(xd, yd, order=args.order, ws=ws)
+        sk.pair(xd, yd, order=args.order, tol=tol, ws=ws)
     torch.cuda.synchronize()
     cnt = sk.counters(ws)
     print(f"# warmup done: k = {k.item():.17g}, status {cnt['status']}", file=sys.stderr,
@@ -185,7 +187,7 @@ def main():
     wall0 = time.perf_counter()
     for i, (e0, e1) in enumerate(evs):
         e0.record(s)
-        kk = sk.pair(xd, yd, order=args.order, ws=ws)
+        kk = sk.pair(xd, yd, order=args.order, tol=tol, ws=ws)
         e1.record(s)
         print(f"# step {i} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -213,7 +215,8 @@ def main():
                                "(Davies-Harte, seed 4), quadratic variation 1 per channel, "
                                "forward",
                    "length": args.length, "d": int(x.shape[1]), "order": cnt["order"],
-                   "tol": 2.0 ** -53, "cells_per_step": cells},
+                   "tol": args.tol or min(2.0 ** -53, 2.0 ** -36 / cells),
+                   "cells_per_step": cells},
         "k": kk.item(),
         "status": cnt["status"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,

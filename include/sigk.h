@@ -64,8 +64,10 @@ extern "C" {
 
 typedef struct sigk_opts {
     double tol;        /* Neumann-depth tolerance per cell: term n is skipped for
-                          the whole wave once |c|^n/(n!)^2 <= tol in every lane.
-                          <= 0 selects 2^-53.                                     */
+                          the whole wave once |c|^n/(n!)^2 <= tol in every lane of
+                          a chunk.  These per-cell bounds add up over the cells
+                          of a pair, so <= 0 selects min(2^-53, 2^-36/cells) with
+                          cells = (lx-1)(ly-1) of the largest pair of the call.   */
     double tail_tol;   /* truncation warning threshold for the last edge
                           coefficient relative to the edge norm; <= 0: 2^-50.     */
     int32_t order;     /* P = coefficients kept per edge series (degree P-1);
@@ -84,7 +86,7 @@ typedef struct sigk_counters {
     uint32_t order; /* compiled edge order P used by the last call          */
 } sigk_counters;
 
-/* Default options (tol 2^-53, tail_tol 2^-50, order 12). host */
+/* Default options (tol by size, tail_tol 2^-50, order 12). host */
 void sigk_default_opts(sigk_opts* o);
 
 /* ---------------------------------------------------------------- one pair */

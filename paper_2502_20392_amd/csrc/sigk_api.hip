@@ -97,8 +97,19 @@ int device_wgs(int P, int D, bool bwd) {
     return value;
 }
 
-void fill_common(FwdArgs& a, const sigk_opts& o, int P, int64_t d) {
-    const double tol = o.tol > 0 ? o.tol : std::ldexp(1.0, -53);
+// Per-cell Neumann tolerance.  A dropped term n is bounded by |c|^n/(n!)^2
+// relative to the edge data, and since the kernel value is a linear function
+// of every cell's local error with O(1) weights, these bounds add up over all
+// cells of a pair.  The default therefore scales with the largest pair:
+// tol = min(2^-53, 2^-36 / cells), an accumulated bound of about 1.5e-11.
+double default_tol(int64_t max_cells) {
+    double t = std::ldexp(1.0, -53);
+    if (max_cells > 0) t = std::min(t, std::ldexp(1.0, -36) / (double)max_cells);
+    return t;
+}
+
+void fill_common(FwdArgs& a, const sigk_opts& o, int P, int64_t d, int64_t max_cells) {
+    const double tol = o.tol > 0 ? o.tol : default_tol(max_cells);
     // Neumann term n bounded by |c|^n/(n!)^2 relative to the edge data; it is
     // applied where |c| > tau_n = (tol (n!)^2)^(1/n).  Fixed depth: tau < 0.
     double lf = 0.0;  // log n!
@@ -182,6 +193,7 @@ struct sigk_plan {
     int64_t pool_points = 0;
     int bwd_grid = 0;                 // workgroups the adjoint scratch is sized for
     uint64_t cells = 0;
+    int64_t max_cells = 0;            // cells of the largest pair
     sigk_opts opts;
     // workspace offsets (bytes)
     size_t o_desc = 0, o_tk = 0, o_tkr = 0, o_prog = 0, o_front = 0, fwd_total = 0;
@@ -239,7 +251,7 @@ extern "C" {
 void sigk_default_opts(sigk_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
-    o->tol = std::ldexp(1.0, -53);
+    o->tol = 0.0;  // chosen by size at launch
     o->tail_tol = std::ldexp(1.0, -50);
     o->order = 12;
 }
@@ -301,7 +313,7 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     if (lx < 2 || ly < 2) return SIGK_OK;
     FwdArgs a;
     std::memset(&a, 0, sizeof a);
-    fill_common(a, op, P, d);
+    fill_common(a, op, P, d, std::max<int64_t>(lx - 1, 0) * std::max<int64_t>(ly - 1, 0));
     a.mode = kModeGram;
     a.symmetric = symmetric ? 1 : 0;
     a.strips = (int)L.strips;
@@ -393,6 +405,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
         q.snap_off = snap;
         snap += (int64_t)S * m * P;
         pl->cells += (uint64_t)(m * n);
+        pl->max_cells = std::max<int64_t>(pl->max_cells, m * n);
     }
     if (prog > INT32_MAX) {
         delete pl;
@@ -490,7 +503,7 @@ int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* 
     if (plan->tickets.empty()) return SIGK_OK;
     FwdArgs a;
     std::memset(&a, 0, sizeof a);
-    fill_common(a, plan->opts, plan->P, plan->d);
+    fill_common(a, plan->opts, plan->P, plan->d, plan->max_cells);
     a.mode = kModeTable;
     a.X = pool;
     a.Y = pool;
@@ -580,7 +593,7 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     // checkpointing forward pass
     FwdArgs a;
     std::memset(&a, 0, sizeof a);
-    fill_common(a, plan->opts, plan->P, plan->d);
+    fill_common(a, plan->opts, plan->P, plan->d, plan->max_cells);
     a.mode = kModeTable;
     a.X = pool;
     a.Y = pool;
