@@ -82,6 +82,50 @@ __device__ __forceinline__ void publish(int* flag, int value) {
     if (lane_id() == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Device-coherent accesses for data exchanged between workgroups without
+// cache maintenance: the producer writes with device-scope stores (written
+// through to the level shared by all XCDs), waits for them to complete and
+// then raises a flag; the consumer polls the flag and reads the data with
+// device-scope loads.  No L2 write-back or invalidation is needed.
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// As wait_at_least, for data read back with load_coherent: no cache
+// invalidation, only ordering of the following loads after the flag.
+__device__ bool wait_flag(const int* flag, int need, WsHeader* h, long long ticks) {
+    int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(v) < need) {
+        const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(2);
+            v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (uniform(v) >= need) break;
+            if (uniform((int)(load_status(h) & SIGK_ERR_WATCHDOG))) return false;
+            const long long now = (long long)__builtin_amdgcn_s_memrealtime();
+            if (now - t0 > ticks) {
+                raise_status(h, SIGK_ERR_WATCHDOG);
+                return false;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return true;
+}
+
+// Raise a flag after store_coherent writes: wait until they have completed
+// (gfx9 counts stores in vmcnt), then store the flag.
+__device__ __forceinline__ void publish_coherent(int* flag, int value) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane_id() == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- geometry
 struct Geo {
     const double* x;  // path along the columns (u direction)

@@ -23,7 +23,7 @@ constexpr int kMaxP = 24;   // largest compiled edge order
     X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32)
 
 // Frontier chunk (columns per progress flag) for edge order P.
-__host__ __device__ constexpr int chunk_cols(int P) { return P <= 8 ? 64 : 32; }
+__host__ __device__ constexpr int chunk_cols(int P) { return 32; }
 // Columns of the increment ring in LDS: it holds [c0-63, c0+chunk) while the
 // steps of chunk c0 run.
 __host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }

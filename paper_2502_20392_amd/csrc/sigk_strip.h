@@ -45,9 +45,8 @@ __device__ __forceinline__ int ring_slot(int col) {
 template <int P, int D>
 struct LdsStrip {
     double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
-    double nrm2[ring_cols(P)];      // |dx_k|^2 of the same columns
     double bin[chunk_cols(P) * P];  // bottom edges of the current chunk (lane 0)
-    double tout[chunk_cols(P) * P]; // top edges of the top lane, current chunk
+    float nrm2[ring_cols(P)];       // |dx_k|^2 of the same columns, rounded up
 };
 
 struct Acc {
@@ -67,6 +66,7 @@ struct Recip {
         for (int k = 0; k <= 2 * P; ++k) {
             v[k] = k == 0 ? 0.0 : 1.0 / (double)k;
             if (P >= 10 && P <= 12) asm volatile("" : "+v"(v[k]));
+            else if (P <= 8 && k > 2) asm volatile("" : "+s"(v[k]));
         }
     }
     __device__ __forceinline__ double operator()(int k) const { return v[k]; }
@@ -175,6 +175,7 @@ struct StripCtx {
     double B[P];        // left-edge series of the lane's current cell
     double Ac[P];       // top-edge series produced at the previous step
     double dy[D];
+    double cn;          // cell coefficient of the next step
     double dymax2;      // max_l |dy_l|^2 over the strip
     int q;              // Neumann depth of the current chunk
     unsigned nvalid;
@@ -195,9 +196,9 @@ struct StripCtx {
         const int CH = chunk_cols(P);
         const int nc = min(CH, g.m - c0);
         if (has_below) {
-            if (!wait_at_least(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
+            if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
             const double* src = Fin + (int64_t)c0 * P;
-            for (int e = lane; e < nc * P; e += kWave) L.bin[e] = src[e];
+            for (int e = lane; e < nc * P; e += kWave) L.bin[e] = load_coherent(&src[e]);
         }
         if (lane < nc) {
             const int col = c0 + lane;
@@ -209,14 +210,14 @@ struct StripCtx {
                 L.dx[ch * ring_cols(P) + ring_slot<P>(col)] = v;
                 n2 = fma(v, v, n2);
             }
-            L.nrm2[ring_slot<P>(col)] = n2;
+            L.nrm2[ring_slot<P>(col)] = (float)(n2 * (1.0 + 1e-6));  // >= n2 after rounding
         }
         __syncthreads();
         // columns touched by steps [c0, c0+CH): [c0-63, c0+nc)
         double w = 0.0;
         const int k1 = c0 - (kWave - 1) + lane, k2 = c0 + lane;
-        if (k1 >= 0 && k1 < c0 + nc) w = L.nrm2[ring_slot<P>(k1)];
-        if (lane < nc) w = fmax(w, L.nrm2[ring_slot<P>(k2)]);
+        if (k1 >= 0 && k1 < c0 + nc) w = (double)L.nrm2[ring_slot<P>(k1)];
+        if (lane < nc) w = fmax(w, (double)L.nrm2[ring_slot<P>(k2)]);
         const double cmax2 = wave_max(w) * dymax2;
         int qq = 0;
 #pragma unroll
@@ -226,16 +227,8 @@ struct StripCtx {
         return true;
     }
 
-    __device__ void flush(int c0, int c1) {
-        const int lane = lane_id();
-        __syncthreads();
-        const int nc = c1 - c0;
-        double* dst = Fout + (int64_t)c0 * P;
-        for (int e = lane; e < nc * P; e += kWave) dst[e] = L.tout[e];
-        tail_check<P>(&L.tout[(lane < nc ? lane : 0) * P], a.tail_tol, lane < nc, acc.status);
-        publish(&prog[s], c1);
-        __syncthreads();
-    }
+    // The top lane has written columns [.., c1) of the frontier: publish them.
+    __device__ void flush(int c1) { publish_coherent(&prog[s], c1); }
 
     __device__ void save_state(int t) {
         // wave state before step t: (B, Ac) of every lane, layout [2P][64]
@@ -246,6 +239,24 @@ struct StripCtx {
             dst[i * kWave + lane] = B[i];
             dst[(P + i) * kWave + lane] = Ac[i];
         }
+    }
+
+    // Cell coefficient c = <dx_col, dy_row> of step t into cn.  For small
+    // orders it is computed one step ahead so that the LDS latency of the
+    // increments overlaps the cell map (several waves share a SIMD there and
+    // registers allow it).  Every ring slot read is inside the LDS array for
+    // any t; where step t starts a new chunk the value read ahead is stale and
+    // is recomputed after load_chunk().
+    static constexpr bool kAhead = P <= 8;
+    __device__ __forceinline__ void prefetch(int t) {
+        const int ri = ring_slot<P>(t - lane_id());
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < D; ch += 2) {
+            c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
+            c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+        }
+        cn = c0 + c1;
     }
 
     // One step: every lane advances one cell along its row.  QC >= 0 fixes the
@@ -263,23 +274,27 @@ struct StripCtx {
 #pragma unroll
             for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
         }
-        const int ri = ring_slot<P>(col);
-        double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < D; ch += 2) {
-            c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
-            c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+        // small orders: coefficient computed one step ahead; large orders
+        // (one wave per SIMD, registers scarce): computed here
+        double c;
+        if constexpr (kAhead) {
+            c = cn;
+            prefetch(t + 1);
+        } else {
+            prefetch(t);
+            c = cn;
         }
         double An[P], Bn[P];
-        cell_map<P>(A, B, c0 + c1, An, Bn, QC >= 0 ? QC : q, R);
+        cell_map<P>(A, B, c, An, Bn, QC >= 0 ? QC : q, R);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             B[i] = Bn[i];
             Ac[i] = An[i];
         }
         if (has_above && lane == kWave - 1 && act) {
+            double* dst = Fout + (int64_t)col * P;
 #pragma unroll
-            for (int i = 0; i < P; ++i) L.tout[(col % CH) * P + i] = An[i];
+            for (int i = 0; i < P; ++i) store_coherent(&dst[i], An[i]);
         }
     }
 
@@ -309,9 +324,13 @@ struct StripCtx {
         while (t < t1) {
             if ((t % CH) == 0 && t < m) {
                 if (!load_chunk(t)) return false;
-                if (t > 0)
-                    tail_check<P>(B, a.tail_tol, lane_ok && t - lane > 0 && t - lane <= m,
-                                  acc.status);
+                if (kAhead) prefetch(t);
+                if (t > 0) {
+                    // sample both edge series of every row once per chunk
+                    const bool done = lane_ok && t - lane > 0 && t - lane <= m;
+                    tail_check<P>(B, a.tail_tol, done, acc.status);
+                    tail_check<P>(Ac, a.tail_tol, done, acc.status);
+                }
             }
             // steps up to the next chunk boundary, flush point or range end
             int te = min(t1, t - (t % CH) + CH);
@@ -341,8 +360,7 @@ struct StripCtx {
             }
             if (has_above) {
                 const int tc = t - 1 - (kWave - 1);
-                if (tc >= 0 && tc < m && ((tc % CH) == CH - 1 || tc == m - 1))
-                    flush(tc - tc % CH, tc + 1);
+                if (tc >= 0 && tc < m && ((tc % CH) == CH - 1 || tc == m - 1)) flush(tc + 1);
             }
         }
         return true;
