@@ -96,6 +96,28 @@ __device__ __forceinline__ double load_coherent(const double* p) {
         (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// n doubles at p read with device-coherent plain loads (buffer loads with the
+// coherence bit that device-scope atomic loads use, but free for the compiler
+// to batch).  Indices outside [0, n) read 0 (hardware range check).
+struct CoherentSpan {
+    __amdgpu_buffer_rsrc_t r;
+    // p and n must be uniform over the wave (made explicit for the compiler,
+    // which needs the descriptor in scalar registers)
+    __device__ CoherentSpan(const double* p, int n) {
+        const uint64_t a = (uint64_t)p;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        void* u = (void*)(((uint64_t)hi << 32) | lo);
+        r = __builtin_amdgcn_make_buffer_rsrc(u, (short)0, __builtin_amdgcn_readfirstlane(n * 8),
+                                              0x00020000);
+    }
+    __device__ __forceinline__ double load(int i) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0,
+                                                                               kCoherentLoad));
+    }
+    static constexpr int kCoherentLoad = 16;  // cache-policy operand: sc1
+};
+
 // As wait_at_least, for data read back with load_coherent: no cache
 // invalidation, only ordering of the following loads after the flag.
 __device__ bool wait_flag(const int* flag, int need, WsHeader* h, long long ticks) {

@@ -20,7 +20,7 @@
 namespace sigk {
 
 template <int P, int D>
-__global__ void __launch_bounds__(kWave) fwd_kernel(FwdArgs a) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 6 && D <= 8 ? 3 : 1))) fwd_kernel(FwdArgs a) {
     __shared__ LdsStrip<P, D> L;
     Acc acc;
     const int lane = lane_id();

@@ -46,6 +46,7 @@ template <int P, int D>
 struct LdsStrip {
     double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
     double bin[chunk_cols(P) * P];  // bottom edges of the current chunk (lane 0)
+    double tout[chunk_cols(P) * P]; // top edges of the top lane, current chunk
     float nrm2[ring_cols(P)];       // |dx_k|^2 of the same columns, rounded up
 };
 
@@ -75,23 +76,27 @@ struct Recip {
 // Algorithmic flops of one cell at edge order P, Neumann depth q, d channels
 // (FMA = 2 flops):
 //   n = 0 : two Horner edge evaluations, 2(P-2) FMA + 2 add       -> 4P - 6
-//   n >= 1: e_n (2 mul), Toeplitz 2(P-n) FMA, Horner sums 2(P-2) FMA,
-//           e_n/(n+1) (1 mul), 2 FMA                               -> 8P - 4n - 1
+//   n >= 1: e_n = c^n/n! (1 mul, none for n = 1), Toeplitz 2(P-n) FMA,
+//           Horner sums 2(P-2) FMA, e_n/(n+1) (1 mul), 2 FMA       -> 8P - 4n - 2
+//                                                            (n = 1: 8P - 7)
 //   Delta : d FMA                                                  -> 2d
 __host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
-    return 4LL * P - 6 + (long long)q * (8LL * P - 1) - 2LL * q * (q + 1) + 2LL * d;
+    return 4LL * P - 6 + (long long)q * (8LL * P - 2) - 2LL * q * (q + 1) - (q > 0 ? 1 : 0) +
+           2LL * d;
 }
 
 // Neumann term N of the cell map (Toeplitz part and Horner-form Hankel part),
-// then the following terms while N < q.  Written as a compile-time recursion
-// so that every coefficient index is a constant (registers, never scratch).
+// then the following terms while N < q.  ep = c^(N-1)/N! from the previous
+// term (1 for N = 1), so e_N = ep c and e_N/(N+1) = e_N (1/(N+1)).  Written
+// as a compile-time recursion so that every coefficient index is a constant
+// (registers, never scratch).
 template <int P, int N>
 __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double (&B)[P],
-                                              double c, double e, double (&An)[P],
+                                              double c, double ep, double (&An)[P],
                                               double (&Bn)[P], int q, const Recip<P>& R) {
     if constexpr (N < P) {
         if (N > q) return;  // scalar, uniform (folds away for a constant q)
-        e = e * c * R(N);
+        const double e = N == 1 ? c : ep * c;
 #pragma unroll
         for (int i = N; i < P; ++i) {
             An[i] = fma(e, A[i - N], An[i]);
@@ -107,7 +112,7 @@ __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double
         const double en = e * R(N + 1);
         An[N] = fma(en, tb, An[N]);
         Bn[N] = fma(en, ta, Bn[N]);
-        neumann_terms<P, N + 1>(A, B, c, e, An, Bn, q, R);
+        neumann_terms<P, N + 1>(A, B, c, en, An, Bn, q, R);
     }
 }
 
@@ -195,22 +200,41 @@ struct StripCtx {
         const int lane = lane_id();
         const int CH = chunk_cols(P);
         const int nc = min(CH, g.m - c0);
+        // Issue every load before the first wait: the path points of the
+        // chunk's columns (lane j: column c0 + j, clamped to the chunk), then
+        // the frontier columns once the strip below has published them.
+        const int col = c0 + min(lane, nc - 1);
+        const double* xp = g.x + (int64_t)col * a.d;
+        double lo[D], hi[D];
+#pragma unroll
+        for (int ch = 0; ch < D; ++ch) {
+            const int cc = ch < a.d ? ch : 0;
+            lo[ch] = xp[cc];
+            hi[ch] = xp[a.d + cc];
+        }
         if (has_below) {
             if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
-            const double* src = Fin + (int64_t)c0 * P;
-            for (int e = lane; e < nc * P; e += kWave) L.bin[e] = load_coherent(&src[e]);
+            constexpr int NB = (chunk_cols(P) * P + kWave - 1) / kWave;
+            const CoherentSpan src(Fin + (int64_t)c0 * P, nc * P);
+            double bv[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) bv[k] = src.load(lane + k * kWave);
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (lane + k * kWave < nc * P) L.bin[lane + k * kWave] = bv[k];
         }
         if (lane < nc) {
-            const int col = c0 + lane;
-            const double* xp = g.x + (int64_t)col * a.d;
             double n2 = 0.0;
 #pragma unroll
             for (int ch = 0; ch < D; ++ch) {
-                const double v = ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
+                const double v = ch < a.d ? hi[ch] - lo[ch] : 0.0;
                 L.dx[ch * ring_cols(P) + ring_slot<P>(col)] = v;
                 n2 = fma(v, v, n2);
             }
-            L.nrm2[ring_slot<P>(col)] = (float)(n2 * (1.0 + 1e-6));  // >= n2 after rounding
+            // stored as a float no smaller than n2 (relative slack above the
+            // float rounding, floor at the smallest normal float)
+            L.nrm2[ring_slot<P>(col)] =
+                (float)fmax(n2 * (1.0 + 1e-6), n2 > 0.0 ? 1.2e-38 : 0.0);
         }
         __syncthreads();
         // columns touched by steps [c0, c0+CH): [c0-63, c0+nc)
@@ -227,8 +251,15 @@ struct StripCtx {
         return true;
     }
 
-    // The top lane has written columns [.., c1) of the frontier: publish them.
-    __device__ void flush(int c1) { publish_coherent(&prog[s], c1); }
+    // The top lane has produced columns [c0, c1) (staged in LDS): write them
+    // to the frontier with coalesced device-coherent stores and publish.
+    __device__ void flush(int c0, int c1) {
+        const int CH = chunk_cols(P);
+        double* dst = Fout + (int64_t)c0 * P;
+        const int base = (c0 % CH) * P;
+        for (int e = lane_id(); e < (c1 - c0) * P; e += kWave) store_coherent(&dst[e], L.tout[base + e]);
+        publish_coherent(&prog[s], c1);
+    }
 
     __device__ void save_state(int t) {
         // wave state before step t: (B, Ac) of every lane, layout [2P][64]
@@ -292,9 +323,9 @@ struct StripCtx {
             Ac[i] = An[i];
         }
         if (has_above && lane == kWave - 1 && act) {
-            double* dst = Fout + (int64_t)col * P;
+            double* dst = &L.tout[(col % chunk_cols(P)) * P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) store_coherent(&dst[i], An[i]);
+            for (int i = 0; i < P; ++i) dst[i] = An[i];
         }
     }
 
@@ -360,7 +391,8 @@ struct StripCtx {
             }
             if (has_above) {
                 const int tc = t - 1 - (kWave - 1);
-                if (tc >= 0 && tc < m && ((tc % CH) == CH - 1 || tc == m - 1)) flush(tc + 1);
+                if (tc >= 0 && tc < m && ((tc % CH) == CH - 1 || tc == m - 1))
+                    flush(tc - tc % CH, tc + 1);
             }
         }
         return true;
