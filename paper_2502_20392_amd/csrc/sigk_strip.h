@@ -141,6 +141,63 @@ __device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], d
     neumann_terms<P, 1>(A, B, c, 1.0, An, Bn, q, R);
 }
 
+// The same map for a compile-time depth Q, in two phases: first everything
+// that needs only the left edge B and c (powers of c, the Hankel sums over B,
+// the Toeplitz terms of B' that do not involve B_0), then the parts that need
+// the bottom edge A (B_0 := A_0).  The first phase covers the latency of the
+// cross-lane move and LDS read that deliver A.  Every sum accumulates in the
+// same order as in cell_map.
+template <int P, int Q>
+struct SplitMap {
+    double e[Q + 1], en[Q + 1], tb[Q + 1];
+
+    __device__ __forceinline__ void pre(const double (&B)[P], double c, double (&Bn)[P],
+                                        const Recip<P>& R) {
+#pragma unroll
+        for (int n = 0; n <= Q; ++n) {
+            if (n > 0) {
+                e[n] = n == 1 ? c : en[n - 1] * c;
+                en[n] = e[n] * R(n + 1);
+            }
+            double t = B[P - 1];
+#pragma unroll
+            for (int r = P - 2; r >= 1; --r) t = fma(t, R(n + r + 1), B[r]);
+            tb[n] = t;
+        }
+#pragma unroll
+        for (int i = 1; i < P; ++i) Bn[i] = B[i];
+#pragma unroll
+        for (int n = 1; n <= Q; ++n)
+#pragma unroll
+            for (int i = n + 1; i < P; ++i) Bn[i] = fma(e[n], B[i - n], Bn[i]);
+    }
+
+    __device__ __forceinline__ void post(const double (&A)[P], double (&An)[P], double (&Bn)[P],
+                                         const Recip<P>& R) {
+#pragma unroll
+        for (int i = 1; i < P; ++i) An[i] = A[i];
+#pragma unroll
+        for (int n = 1; n <= Q; ++n) {
+#pragma unroll
+            for (int i = n; i < P; ++i) An[i] = fma(e[n], A[i - n], An[i]);
+            Bn[n] = fma(e[n], A[0], Bn[n]);
+        }
+        double t = A[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) t = fma(t, R(r + 1), A[r]);
+        An[0] = A[0] + tb[0];
+        Bn[0] = A[0] + t;
+#pragma unroll
+        for (int n = 1; n <= Q; ++n) {
+            double ta = A[P - 1];
+#pragma unroll
+            for (int r = P - 2; r >= 1; --r) ta = fma(ta, R(n + r + 1), A[r]);
+            An[n] = fma(en[n], tb[n], An[n]);
+            Bn[n] = fma(en[n], ta, Bn[n]);
+        }
+    }
+};
+
 // Edge-series tail check: last coefficient's weight against the edge norm.
 template <int P>
 __device__ __forceinline__ void tail_check(const double* v, double tail_tol, bool act,
@@ -299,6 +356,31 @@ struct StripCtx {
         const int col = t - lane;
         double A[P];
         const double* bsrc = &L.bin[(t % CH) * P];
+        if constexpr (kAhead && !EDGE && QC >= 0) {
+            // steady state, depth known at compile time: B-only work first
+            double bv[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) bv[i] = bsrc[i];
+            double An[P], Bn[P];
+            SplitMap<P, QC> S;
+            S.pre(B, cn, Bn, R);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bv[i]);
+            S.post(A, An, Bn, R);
+            prefetch(t + 1);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                B[i] = Bn[i];
+                Ac[i] = An[i];
+            }
+            if (has_above && lane == kWave - 1 && act) {
+                double* dst = &L.tout[(col % chunk_cols(P)) * P];
+#pragma unroll
+                for (int i = 0; i < P; ++i) dst[i] = An[i];
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
         if (EDGE && col == 0) {
