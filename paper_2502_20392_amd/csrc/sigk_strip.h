@@ -361,6 +361,11 @@ struct StripCtx {
             double bv[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) bv[i] = bsrc[i];
+            // increments of the next step's column, consumed after the map
+            const int ri = ring_slot<P>(t + 1 - lane);
+            double dxv[D];
+#pragma unroll
+            for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * ring_cols(P) + ri];
             double An[P], Bn[P];
             SplitMap<P, QC> S;
             S.pre(B, cn, Bn, R);
@@ -368,7 +373,14 @@ struct StripCtx {
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bv[i]);
             S.post(A, An, Bn, R);
-            prefetch(t + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < D; ch += 2) {
+                c0 = fma(dy[ch], dxv[ch], c0);
+                c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
+            }
+            cn = c0 + c1;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 B[i] = Bn[i];
