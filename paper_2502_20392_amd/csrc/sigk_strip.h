@@ -221,6 +221,22 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Copy of P doubles between registers and 16-byte aligned LDS rows, in
+// 16-byte accesses where P is even.
+template <int P>
+__device__ __forceinline__ void lds_copy(double* dst, const double* src) {
+    if constexpr (P % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < P; i += 2) {
+            const double2 v = *(const double2*)(src + i);
+            *(double2*)(dst + i) = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < P; ++i) dst[i] = src[i];
+    }
+}
+
 template <int P, int D>
 struct StripCtx {
     const FwdArgs& a;
@@ -355,12 +371,11 @@ struct StripCtx {
         const int CH = chunk_cols(P);
         const int col = t - lane;
         double A[P];
-        const double* bsrc = &L.bin[(t % CH) * P];
+        const double* bsrc = &L.bin[((unsigned)t % (unsigned)CH) * P];  // t >= 0
         if constexpr (kAhead && !EDGE && QC >= 0) {
             // steady state, depth known at compile time: B-only work first
             double bv[P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) bv[i] = bsrc[i];
+            lds_copy<P>(bv, bsrc);
             // increments of the next step's column, consumed after the map
             const int ri = ring_slot<P>(t + 1 - lane);
             double dxv[D];
@@ -387,9 +402,8 @@ struct StripCtx {
                 Ac[i] = An[i];
             }
             if (has_above && lane == kWave - 1 && act) {
-                double* dst = &L.tout[(col % chunk_cols(P)) * P];
-#pragma unroll
-                for (int i = 0; i < P; ++i) dst[i] = An[i];
+                double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P)) * P];
+                lds_copy<P>(dst, An);
             }
             return;
         }
@@ -417,7 +431,7 @@ struct StripCtx {
             Ac[i] = An[i];
         }
         if (has_above && lane == kWave - 1 && act) {
-            double* dst = &L.tout[(col % chunk_cols(P)) * P];
+            double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P)) * P];
 #pragma unroll
             for (int i = 0; i < P; ++i) dst[i] = An[i];
         }
@@ -435,7 +449,7 @@ struct StripCtx {
         }
         constexpr int QC = P <= 8 ? QD : -1;
         for (; t < te; ++t) {
-            if (ck && (t % ck_every) == 0) save_state(t);
+            if (ck && ((unsigned)t % (unsigned)ck_every) == 0) save_state(t);
             step<false, QC>(t, lane_ok);
         }
     }
@@ -469,7 +483,7 @@ struct StripCtx {
             const long long fl = cell_flops(P, q, a.d);
             if (EDGE) {
                 for (; t < te; ++t) {
-                    if (ck && (t % ck_every) == 0) save_state(t);
+                    if (ck && ((unsigned)t % (unsigned)ck_every) == 0) save_state(t);
                     const int col = t - lane;
                     const bool act = lane_ok && col >= 0 && col < m;
                     const unsigned cnt = (unsigned)__builtin_popcountll(ballot(act));
