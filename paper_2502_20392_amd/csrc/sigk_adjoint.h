@@ -26,22 +26,47 @@
 
 namespace sigk {
 
-// Hankel sums hB_n, hA_n for n = N..q (Horner form, as in the forward).
+// Powers e_n = c^n/n!, n = N..q (e[0] = 1).
 template <int P, int N>
-__device__ __forceinline__ void hankel_sums(const double (&A)[P], const double (&B)[P], int q,
-                                            double (&hA)[P], double (&hB)[P],
-                                            const Recip<P>& R) {
+__device__ __forceinline__ void powers(double c, int q, double (&e)[P], const Recip<P>& R) {
     if constexpr (N < P) {
         if (N > q) return;
-        double tb = B[P - 1], ta = A[P - 1];
+        e[N] = e[N - 1] * c * R(N);
+        powers<P, N + 1>(c, q, e, R);
+    }
+}
+
+// Hankel sums of one edge, h_n = sum_{r>=1} V_r n!/(n+r)!, n = N..q (Horner
+// form, as in the forward map).
+template <int P, int N>
+__device__ __forceinline__ void hankel_sum(const double (&V)[P], int q, double (&h)[P],
+                                           const Recip<P>& R) {
+    if constexpr (N < P) {
+        if (N > q) return;
+        double t = V[P - 1];
 #pragma unroll
-        for (int r = P - 2; r >= 1; --r) {
-            tb = fma(tb, R(N + r + 1), B[r]);
-            ta = fma(ta, R(N + r + 1), A[r]);
-        }
-        hB[N] = tb * R(N + 1);
-        hA[N] = ta * R(N + 1);
-        hankel_sums<P, N + 1>(A, B, q, hA, hB, R);
+        for (int r = P - 2; r >= 1; --r) t = fma(t, R(N + r + 1), V[r]);
+        h[N] = t * R(N + 1);
+        hankel_sum<P, N + 1>(V, q, h, R);
+    }
+}
+
+// Left edge of a cell from its right edge.  The map B -> B' is unit lower
+// triangular Toeplitz plus terms in A only:
+//     B'_j = B_j + sum_{n=1}^{min(j,q)} e_n B_{j-n} + [j<=q] e_j hA_j,  B_0 := A_0,
+// so B_j (j >= 1) follows by forward substitution.  On entry B holds B',
+// on exit the cell's left edge with B_0 = A_0.
+template <int P, int J>
+__device__ __forceinline__ void unmap_left(const double (&A)[P], double (&B)[P],
+                                           const double (&e)[P], const double (&hA)[P], int q) {
+    if constexpr (J < P) {
+        double t = B[J];
+        if (J <= q) t = fma(-e[J], hA[J], t);
+#pragma unroll
+        for (int n = 1; n <= J; ++n)
+            if (n <= q) t = fma(-e[n], B[J - n], t);
+        B[J] = t;
+        unmap_left<P, J + 1>(A, B, e, hA, q);
     }
 }
 
@@ -80,19 +105,35 @@ __device__ __forceinline__ void adjoint_terms(const double (&A)[P], const double
     }
 }
 
-// Adjoint of cell_map.  A, Bin: the cell's inputs; lAo, lBo: cotangents of its
-// outputs.  Writes the input cotangents lA, lB and returns dL/dc.
+// Adjoint of cell_map, run backwards in time.  A: the cell's bottom edge
+// (stored by the recompute); B: on entry the cell's right edge (the left edge
+// of the next cell of the row), on exit the cell's left edge (recovered by
+// unmap_left, or the boundary series at the path's start when `boundary`).
+// Where `live` is false (steps past the end of the row) B is left unchanged:
+// the recompute holds the row's last right edge there, so the walk back starts
+// from it exactly.  lAo, lBo: cotangents of the outputs.  Writes the input
+// cotangents lA, lB and returns dL/dc.  The recovered left edge differs from
+// the forward one by rounding only; it enters dL/dc, never the cotangents
+// (those depend on c alone).
 template <int P>
-__device__ __forceinline__ double cell_adjoint(const double (&A)[P], const double (&Bin)[P],
-                                               double c, int q, const double (&lAo)[P],
+__device__ __forceinline__ double cell_adjoint(const double (&A)[P], double (&B)[P], double c,
+                                               int q, bool boundary, bool live,
+                                               const double (&lAo)[P],
                                                const double (&lBo)[P], double (&lA)[P],
                                                double (&lB)[P], const Recip<P>& R) {
-    double B[P];
-    B[0] = A[0];
+    double e[P], hA[P], hB[P];
+    e[0] = 1.0;
+    powers<P, 1>(c, q, e, R);
+    hankel_sum<P, 1>(A, q, hA, R);
+    if (boundary) {
 #pragma unroll
-    for (int r = 1; r < P; ++r) B[r] = Bin[r];
-    double hA[P], hB[P];
-    hankel_sums<P, 1>(A, B, q, hA, hB, R);
+        for (int r = 1; r < P; ++r) B[r] = 0.0;
+    } else if (live) {
+        B[0] = A[0];
+        unmap_left<P, 1>(A, B, e, hA, q);
+    }
+    B[0] = A[0];
+    hankel_sum<P, 1>(B, q, hB, R);
     // n = 0 terms: identity parts and the constant-term Hankel rows
 #pragma unroll
     for (int r = 0; r < P; ++r) {

@@ -231,7 +231,7 @@ void plan_layout(sigk_plan& p) {
     o = align256(o + sizeof(double) * (size_t)std::max<int64_t>(p.pool_points * p.d, 1));
     p.o_scr = o;
     p.bwd_grid = kBwdMaxGrid;
-    o = align256(o + sizeof(double) * (size_t)p.bwd_grid * kCkptEvery * 2 * p.P * kWave);
+    o = align256(o + sizeof(double) * (size_t)p.bwd_grid * kCkptEvery * p.P * kWave);
     p.bwd_total = o;
 }
 

@@ -9,9 +9,10 @@
 //   bwd_kernel:  the adjoint sweep, strips in reverse topological order (top
 //                strip of each pair first).  Per segment of kCkptEvery steps,
 //                taken last to first: restore the wave state, recompute the
-//                segment forward while storing each step's cell inputs in a
-//                per-workgroup scratch, then run the adjoint cell map over the
-//                segment in reverse step order.  dL/dc of every cell is chained
+//                segment forward while storing each step's bottom-edge inputs
+//                in a per-workgroup scratch, then run the adjoint cell map over
+//                the segment in reverse step order, recovering each cell's left
+//                edge from its right edge (the left-edge update is triangular).  dL/dc of every cell is chained
 //                into dL/d(increment) of both paths: the x side through an LDS
 //                ring indexed by column (each column is complete once lane 0 has
 //                passed it), the y side in registers of the row's lane.
@@ -237,12 +238,9 @@ struct StripBwd {
 #pragma unroll
                     for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
                 }
-                double* dst = scratch + (int64_t)(t - t0) * (2 * P * kWave);
+                double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    dst[i * kWave + lane] = A[i];
-                    dst[(P + i) * kWave + lane] = B[i];
-                }
+                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
                 const int ri = ring_slot<P>(col);
                 double c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -252,23 +250,23 @@ struct StripBwd {
                 }
                 double An[P], Bn[P];
                 cell_map<P>(A, B, c0 + c1, An, Bn, q, R);
+                // past the end of the row B keeps the row's last right edge
+                const bool live = col < m;
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
-                    B[i] = Bn[i];
+                    B[i] = live ? Bn[i] : B[i];
                     Ac[i] = An[i];
                 }
             }
-            // ---- adjoint over the segment, last step first
+            // ---- adjoint over the segment, last step first; B walks back from
+            // the right edge after the segment to each cell's left edge
             for (int t = t1 - 1; t >= t0; --t) {
                 const int col = t - lane;
                 const bool act = lane_ok && col >= 0 && col < m;
-                const double* src = scratch + (int64_t)(t - t0) * (2 * P * kWave);
-                double A[P], B[P];
+                const double* src = scratch + (int64_t)(t - t0) * (P * kWave);
+                double A[P];
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    A[i] = src[i * kWave + lane];
-                    B[i] = src[(P + i) * kWave + lane];
-                }
+                for (int i = 0; i < P; ++i) A[i] = src[i * kWave + lane];
                 const int ri = ring_slot<P>(col);
                 double dxv[D];
                 double c0 = 0.0, c1 = 0.0;
@@ -306,7 +304,7 @@ struct StripBwd {
                     for (int i = 0; i < P; ++i) lBst[i] = 0.0;
                 }
                 double lA[P], lB[P];
-                double gc = cell_adjoint<P>(A, B, c, q, lAo, lBst, lA, lB, R);
+                double gc = cell_adjoint<P>(A, B, c, q, col == 0, col < m, lAo, lBst, lA, lB, R);
                 if (!act) gc = 0.0;
 #pragma unroll
                 for (int ch = 0; ch < D; ++ch) gy[ch] = fma(gc, dxv[ch], gy[ch]);
@@ -346,7 +344,7 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
     __shared__ LdsBwd<P, D> L;
     const FwdArgs& a = b.f;
     const int lane = lane_id();
-    double* scratch = b.scratch + (int64_t)blockIdx.x * (kCkptEvery * 2 * P * kWave);
+    double* scratch = b.scratch + (int64_t)blockIdx.x * (kCkptEvery * P * kWave);
     for (;;) {
         unsigned t = 0;
         if (lane == 0) t = atomicAdd(&a.hdr->ticket2, 1u);

@@ -108,7 +108,7 @@ struct BwdArgs {
     double* lam_front;       // adjoint frontier (one row per pair, [m][P])
     int* lam_prog;           // adjoint progress counters (columns done from the right)
     double* gdx;             // [sum len][d]: dL/d(increment) at the increment's first point
-    double* scratch;         // per workgroup: kCkptEvery x 2P x 64 recomputed cell inputs
+    double* scratch;         // per workgroup: kCkptEvery x P x 64 recomputed bottom edges
 };
 
 // Launchers implemented per variant (one translation unit each).
