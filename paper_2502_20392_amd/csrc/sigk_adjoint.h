@@ -158,4 +158,108 @@ __device__ __forceinline__ double cell_adjoint(const double (&A)[P], double (&B)
     return g;
 }
 
+// The same adjoint for a depth Q fixed at compile time (no per-term branches).
+// The Hankel transposes are summed over n first, in nested form: for r >= 1,
+//     sum_{n=1}^{Q} e_n lA'_n n!/(n+r)!
+//         = (1/(r+1)!) [u_1 + (1/(r+2)) [u_2 + ... + (1/(Q+r)) u_Q]],
+// with u_n = c^n lA'_n: one FMA per (n, r) instead of a multiply and an add.
+template <int P, int Q>
+__device__ __forceinline__ double cell_adjoint_fixed(const double (&A)[P], double (&B)[P],
+                                                     double c, bool boundary, bool live,
+                                                     const double (&lAo)[P],
+                                                     const double (&lBo)[P], double (&lA)[P],
+                                                     double (&lB)[P], const Recip<P>& R) {
+    double e[Q + 1], cp[Q + 1], hA[Q + 1], hB[Q + 1];
+    e[0] = 1.0;
+    cp[0] = 1.0;
+#pragma unroll
+    for (int n = 1; n <= Q; ++n) {
+        cp[n] = n == 1 ? c : cp[n - 1] * c;
+        e[n] = e[n - 1] * R(n) * c;
+    }
+#pragma unroll
+    for (int n = 1; n <= Q; ++n) {
+        double t = A[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) t = fma(t, R(n + r + 1), A[r]);
+        hA[n] = t * R(n + 1);
+    }
+    if (boundary) {
+#pragma unroll
+        for (int r = 1; r < P; ++r) B[r] = 0.0;
+    } else if (live) {
+        // left edge from right edge: forward substitution (see unmap_left)
+        B[0] = A[0];
+#pragma unroll
+        for (int j = 1; j < P; ++j) {
+            double t = B[j];
+            if (j <= Q) t = fma(-e[j <= Q ? j : 0], hA[j <= Q ? j : 0], t);
+#pragma unroll
+            for (int n = 1; n <= Q && n <= j; ++n) t = fma(-e[n], B[j - n], t);
+            B[j] = t;
+        }
+    }
+    B[0] = A[0];
+#pragma unroll
+    for (int n = 1; n <= Q; ++n) {
+        double t = B[P - 1];
+#pragma unroll
+        for (int r = P - 2; r >= 1; --r) t = fma(t, R(n + r + 1), B[r]);
+        hB[n] = t * R(n + 1);
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        lA[r] = lAo[r];
+        lB[r] = lBo[r];
+    }
+    {
+        // n = 0 rows: d A'_0 / d B_r = d B'_0 / d A_r = 1/r!
+        double f = 1.0;
+#pragma unroll
+        for (int r = 1; r < P; ++r) {
+            f *= R(r);
+            lB[r] = fma(lAo[0], f, lB[r]);
+            lA[r] = fma(lBo[0], f, lA[r]);
+        }
+    }
+    double g = 0.0;
+#pragma unroll
+    for (int n = 1; n <= Q; ++n) {
+        double corr = fma(lAo[n], hB[n], lBo[n] * hA[n]);
+#pragma unroll
+        for (int r = 0; r + n < P; ++r) {
+            lA[r] = fma(e[n], lAo[r + n], lA[r]);
+            lB[r] = fma(e[n], lBo[r + n], lB[r]);  // r = 0 entry: cotangent of B_0 := A_0
+            corr = fma(lAo[r + n], A[r], corr);
+            corr = fma(lBo[r + n], B[r], corr);
+        }
+        g = fma(e[n - 1], corr, g);
+    }
+    if constexpr (Q >= 1) {
+        double ua[Q + 1], ub[Q + 1];
+#pragma unroll
+        for (int n = 1; n <= Q; ++n) {
+            ua[n] = cp[n] * lAo[n];
+            ub[n] = cp[n] * lBo[n];
+        }
+        double f = 1.0;  // 1/(r+1)!
+#pragma unroll
+        for (int r = 1; r < P; ++r) {
+            f *= R(r + 1);
+            double sa = ua[Q], sb = ub[Q];
+#pragma unroll
+            for (int n = Q - 1; n >= 1; --n) {
+                sa = fma(sa, R(n + r + 1), ua[n]);
+                sb = fma(sb, R(n + r + 1), ub[n]);
+            }
+            lB[r] = fma(sa, f, lB[r]);
+            lA[r] = fma(sb, f, lA[r]);
+        }
+    }
+    // B_0 := A_0: its cotangent goes to A_0
+    lA[0] += lB[0];
+    lB[0] = 0.0;
+    return g;
+}
+
 }  // namespace sigk

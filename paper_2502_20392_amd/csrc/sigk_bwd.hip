@@ -175,6 +175,141 @@ struct StripBwd {
         return uniform((int)ckq[k]);
     }
 
+    double lAprev[P];  // bottom-edge cotangents of the previous (later) step
+    double lBst[P];    // left-edge cotangent carried along the row
+    int topl;          // lane whose top-edge cotangent comes from outside the wave
+
+    // Depth dispatch: one specialised segment loop per Neumann depth.
+    template <int Q>
+    __device__ __forceinline__ void segment_at_depth(int q, int t0, int t1) {
+        if constexpr (Q < P - 1) {
+            if (q > Q) {
+                segment_at_depth<Q + 1>(q, t0, t1);
+                return;
+            }
+        }
+        segment<Q>(q, t0, t1);
+    }
+
+    // One segment [t0, t1) of kCkptEvery steps: recompute it forward from its
+    // checkpoint, storing each step's bottom edges, then run the adjoint steps
+    // last to first.  Q >= 0: depth fixed at compile time (== q); Q < 0: q.
+    template <int Q>
+    __device__ void segment(int q, int t0, int t1) {
+        const int lane = lane_id();
+        const int CH = chunk_cols(P);
+        const int W = kCkptEvery;
+        double B[P], Ac[P];
+        {
+            const double* src = ck + (int64_t)(t0 / W) * (2 * P * kWave);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                B[i] = src[i * kWave + lane];
+                Ac[i] = src[(P + i) * kWave + lane];
+            }
+        }
+        for (int t = t0; t < t1; ++t) {
+            const int col = t - lane;
+            double A[P];
+            const double* bsrc = &L.bin[(t % CH) * P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
+            if (col == 0) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+            }
+            double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
+#pragma unroll
+            for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+            const int ri = ring_slot<P>(col);
+            double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < D; ch += 2) {
+                c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
+                c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+            }
+            double An[P], Bn[P];
+            cell_map<P>(A, B, c0 + c1, An, Bn, Q >= 0 ? Q : q, R);
+            // past the end of the row B keeps the row's last right edge
+            const bool live = col < m;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                B[i] = live ? Bn[i] : B[i];
+                Ac[i] = An[i];
+            }
+        }
+        // adjoint over the segment, last step first; B walks back from the
+        // right edge after the segment to each cell's left edge
+        for (int t = t1 - 1; t >= t0; --t) {
+            const int col = t - lane;
+            const bool act = lane_ok && col >= 0 && col < m;
+            const double* src = scratch + (int64_t)(t - t0) * (P * kWave);
+            double A[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) A[i] = src[i * kWave + lane];
+            const int ri = ring_slot<P>(col);
+            double dxv[D];
+            double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < D; ch += 2) {
+                dxv[ch] = L.dx[ch * ring_cols(P) + ri];
+                dxv[ch + 1] = L.dx[(ch + 1) * ring_cols(P) + ri];
+                c0 = fma(dy[ch], dxv[ch], c0);
+                c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
+            }
+            const double c = c0 + c1;
+            // cotangent of the top edge: from the lane above, the strip above
+            // (top lane of a full strip) or the seed of the corner cell
+            const int tcol = t - topl;  // column of the top lane at this step
+            double lAo[P];
+            if (has_above) {
+                const double* lsrc = &L.lin[(((tcol >= 0 ? tcol : 0) / CH) & 1) * CH * P +
+                                            ((tcol >= 0 ? tcol : 0) % CH) * P];
+#pragma unroll
+                for (int i = 0; i < P; ++i) lAo[i] = shift_down(lAprev[i], lsrc[i]);
+            } else {
+                const bool corner = col == m - 1;
+                double f = seed_scale;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const double topv = corner ? f : 0.0;
+                    lAo[i] = shift_down(lAprev[i], topv);
+                    if (nrows < kWave) lAo[i] = lane == topl ? topv : lAo[i];
+                    f = f * R(i + 1);
+                }
+            }
+            if (col == m - 1) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) lBst[i] = 0.0;
+            }
+            double lA[P], lB[P];
+            double gc;
+            if constexpr (Q >= 0)
+                gc = cell_adjoint_fixed<P, Q>(A, B, c, col == 0, col < m, lAo, lBst, lA, lB, R);
+            else
+                gc = cell_adjoint<P>(A, B, c, q, col == 0, col < m, lAo, lBst, lA, lB, R);
+            if (!act) gc = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < D; ++ch) gy[ch] = fma(gc, dxv[ch], gy[ch]);
+            if (act) {
+#pragma unroll
+                for (int ch = 0; ch < D; ++ch) {
+                    double& gv = L.gx[ch * ring_cols(P) + ri];
+                    gv = fma(gc, dy[ch], gv);
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) L.lout[(col % CH) * P + i] = lA[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                lBst[i] = lB[i];
+                lAprev[i] = lA[i];
+            }
+        }
+    }
+
     __device__ bool sweep() {
         const int lane = lane_id();
         const int CH = chunk_cols(P);
@@ -205,126 +340,22 @@ struct StripBwd {
         __syncthreads();
 
         const int T = m + nrows - 1;
-        double lAprev[P], lBst[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             lAprev[i] = 0.0;
             lBst[i] = 0.0;
         }
-        const int topl = has_above ? kWave - 1 : nrows - 1;
+        topl = has_above ? kWave - 1 : nrows - 1;
         for (int t0 = ((T - 1) / W) * W; t0 >= 0; t0 -= W) {
             const int t1 = min(t0 + W, T);
             const int q = depth_at(t0);
             load_dx_down_to(max(t0 - (kWave - 1), 0));
             if (has_above && !load_lin_down_to(max(t0 - (kWave - 1), 0))) return false;
             if (t0 < m && t0 / CH != bin_chunk) load_bin(t0 / CH);
-            // ---- recompute the segment forward, keeping each step's inputs
-            double B[P], Ac[P];
-            {
-                const double* src = ck + (int64_t)(t0 / W) * (2 * P * kWave);
-#pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    B[i] = src[i * kWave + lane];
-                    Ac[i] = src[(P + i) * kWave + lane];
-                }
-            }
-            for (int t = t0; t < t1; ++t) {
-                const int col = t - lane;
-                double A[P];
-                const double* bsrc = &L.bin[(t % CH) * P];
-#pragma unroll
-                for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
-                if (col == 0) {
-#pragma unroll
-                    for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
-                }
-                double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
-#pragma unroll
-                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
-                const int ri = ring_slot<P>(col);
-                double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-                for (int ch = 0; ch < D; ch += 2) {
-                    c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
-                    c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
-                }
-                double An[P], Bn[P];
-                cell_map<P>(A, B, c0 + c1, An, Bn, q, R);
-                // past the end of the row B keeps the row's last right edge
-                const bool live = col < m;
-#pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    B[i] = live ? Bn[i] : B[i];
-                    Ac[i] = An[i];
-                }
-            }
-            // ---- adjoint over the segment, last step first; B walks back from
-            // the right edge after the segment to each cell's left edge
-            for (int t = t1 - 1; t >= t0; --t) {
-                const int col = t - lane;
-                const bool act = lane_ok && col >= 0 && col < m;
-                const double* src = scratch + (int64_t)(t - t0) * (P * kWave);
-                double A[P];
-#pragma unroll
-                for (int i = 0; i < P; ++i) A[i] = src[i * kWave + lane];
-                const int ri = ring_slot<P>(col);
-                double dxv[D];
-                double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-                for (int ch = 0; ch < D; ch += 2) {
-                    dxv[ch] = L.dx[ch * ring_cols(P) + ri];
-                    dxv[ch + 1] = L.dx[(ch + 1) * ring_cols(P) + ri];
-                    c0 = fma(dy[ch], dxv[ch], c0);
-                    c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
-                }
-                const double c = c0 + c1;
-                // cotangent of the top edge: from the lane above, the strip above
-                // (top lane of a full strip) or the seed of the corner cell
-                const int tcol = t - topl;  // column of the top lane at this step
-                double lAo[P];
-                if (has_above) {
-                    const double* lsrc =
-                        &L.lin[(((tcol >= 0 ? tcol : 0) / CH) & 1) * CH * P +
-                               ((tcol >= 0 ? tcol : 0) % CH) * P];
-#pragma unroll
-                    for (int i = 0; i < P; ++i) lAo[i] = shift_down(lAprev[i], lsrc[i]);
-                } else {
-                    const bool corner = col == m - 1;
-                    double f = seed_scale;
-#pragma unroll
-                    for (int i = 0; i < P; ++i) {
-                        const double topv = corner ? f : 0.0;
-                        lAo[i] = shift_down(lAprev[i], topv);
-                        if (nrows < kWave) lAo[i] = lane == topl ? topv : lAo[i];
-                        f = f * R(i + 1);
-                    }
-                }
-                if (col == m - 1) {
-#pragma unroll
-                    for (int i = 0; i < P; ++i) lBst[i] = 0.0;
-                }
-                double lA[P], lB[P];
-                double gc = cell_adjoint<P>(A, B, c, q, col == 0, col < m, lAo, lBst, lA, lB, R);
-                if (!act) gc = 0.0;
-#pragma unroll
-                for (int ch = 0; ch < D; ++ch) gy[ch] = fma(gc, dxv[ch], gy[ch]);
-                if (act) {
-#pragma unroll
-                    for (int ch = 0; ch < D; ++ch) {
-                        double& gv = L.gx[ch * ring_cols(P) + ri];
-                        gv = fma(gc, dy[ch], gv);
-                    }
-                    if (lane == 0) {
-#pragma unroll
-                        for (int i = 0; i < P; ++i) L.lout[(col % CH) * P + i] = lA[i];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    lBst[i] = lB[i];
-                    lAprev[i] = lA[i];
-                }
-            }
+            if constexpr (P <= 12)
+                segment_at_depth<0>(q, t0, t1);
+            else
+                segment<-1>(q, t0, t1);
             if (t0 < m && (t0 % CH) == 0) flush_cols(t0, min(t0 + CH, m));
         }
         // dL/d(dy_l) of this lane's row
