@@ -151,3 +151,38 @@ def test_mmd_full_size_finite_differences(dev):
         assert abs(fd - grad[c]) <= 1e-6 * max(1e-3, abs(grad).max()), (c, fd, grad[c])
     # translation invariance: gradients over the points of each path sum to zero
     assert np.abs(grad.sum(axis=1)).max() <= 1e-10 * max(1, np.abs(grad).max())
+
+
+@pytest.mark.parametrize("order", [8, 10, 12, 16])
+def test_gradient_fixed_and_runtime_depth(dev, order):
+    """Orders up to 12 run depth-specialised adjoint loops, larger orders the
+    runtime-depth loop; both against the oracle on the same smooth pair (several
+    checkpoint segments, ragged strip and segment tails)."""
+    g = synth.rng(4200)
+    x = np.cumsum(g.normal(size=(90, 3)) * 0.02, axis=0)
+    y = np.cumsum(g.normal(size=(75, 3)) * 0.02, axis=0)
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=order)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-11 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-10 * sc
+    assert np.abs(gy - gy0).max() <= 1e-10 * sc
+    assert sk().counters()["status"] == 0
+
+
+@pytest.mark.parametrize("order", [12, 16])
+def test_rough_gradient(dev, order):
+    """Rough paths (|c| up to ~0.3): the adjoint recovers each cell's left edge
+    from its right edge; check the gradient against the oracle (1e-8, the
+    roughest-input tolerance)."""
+    g = synth.rng(4300)
+    sig = 0.17 if order == 16 else 0.12
+    x = np.cumsum(g.normal(size=(60, 4)) * sig, axis=0)
+    y = np.cumsum(g.normal(size=(50, 4)) * sig, axis=0)
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=order)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-10 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-8 * sc
+    assert np.abs(gy - gy0).max() <= 1e-8 * sc
+    assert sk().counters()["status"] == 0
