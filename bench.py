@@ -45,6 +45,9 @@ def parse():
                     help="points of the prefix pair the CPU oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", default="",
+                    help="run only the extra workloads whose name contains this text and print "
+                         "their JSON (for profiling runs)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -89,26 +92,40 @@ def timed(fn, torch, steps=3):
     return best
 
 
-def extras(torch, sk, dev):
+def extras(torch, sk, dev, only=""):
     import synth
     import paper_2502_20392_amd.tune as tune
     res = {}
+
+    def want(name):
+        return only in name
 
     def frac(flops, ms):
         return flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS
 
     for name, sig, order in (("gram64_len1024_d16_sigma1", 1.0, 12),
                              ("gram64_len1024_d16_sigma4", 4.0, 20)):
+        if not want(name):
+            continue
         X = torch.from_numpy(synth.gram_mid(sig)).to(dev)
         ms = timed(lambda: sk.gram(X, order=order), torch)
         c = sk.counters()
         res[name] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": order,
                      "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
-    X = torch.from_numpy(synth.gram_small()).to(dev)
-    ms = timed(lambda: sk.gram(X, order=12), torch)
-    c = sk.counters()
-    res["gram8_len128_d3"] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": 12,
-                              "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+    if want("gram8_len128_d3"):
+        X = torch.from_numpy(synth.gram_small()).to(dev)
+        ms = timed(lambda: sk.gram(X, order=12), torch)
+        c = sk.counters()
+        res["gram8_len128_d3"] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": 12,
+                                  "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+    if want("ragged512_len64to4096_d32_graph"):
+        ragged(torch, sk, dev, synth, tune, frac, res)
+    if want("mmd_32x32_len2048_d8_fwd_bwd"):
+        mmd(torch, sk, dev, synth, res)
+    return res
+
+
+def ragged(torch, sk, dev, synth, tune, frac, res):
     # ragged batch: autotuned order and grid, one persistent launch in a HIP graph
     pool, off, pairs = synth.ragged_paths()
     pd = torch.from_numpy(pool).to(dev)
@@ -122,6 +139,9 @@ def extras(torch, sk, dev):
     res["ragged512_len64to4096_d32_graph"] = {
         "cells_per_s": plan.cells / (ms / 1e3), "ms": ms, "order": tuned["order"],
         "grid": tuned["grid"], "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+
+
+def mmd(torch, sk, dev, synth, res):
     # MMD^2 forward + backward (gradient with respect to X)
     Xm, Ym = synth.mmd_sets()
     Xt = torch.from_numpy(Xm).to(dev).requires_grad_(True)
@@ -141,7 +161,6 @@ def extras(torch, sk, dev):
         "cells_per_s": fwd_cells / (ms / 1e3), "ms": ms, "order": 10,
         "fwd_cells": fwd_cells, "bwd_cells": bwd_cells,
         "note": "fwd+bwd: forward cells over the time of forward plus backward"}
-    return res
 
 
 def main():
@@ -155,6 +174,9 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.only:
+        print(json.dumps(extras(torch, sk, dev, args.only)))
+        return
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)
