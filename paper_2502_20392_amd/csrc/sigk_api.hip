@@ -30,13 +30,14 @@ struct Variant {
     int (*occ_fwd)();
     hipError_t (*ckpt)(const FwdArgs&, int, hipStream_t);
     hipError_t (*bwd)(const BwdArgs&, int, hipStream_t);
+    int (*occ_ckpt)();
     int (*occ_bwd)();
 };
 
-#define SIGK_V_FWD(P, D) {P, D, launch_fwd_##P##_##D, occupancy_fwd_##P##_##D, nullptr, nullptr, nullptr},
+#define SIGK_V_FWD(P, D) {P, D, launch_fwd_##P##_##D, occupancy_fwd_##P##_##D, nullptr, nullptr, nullptr, nullptr},
 const Variant kFwdTable[] = {SIGK_FWD_VARIANTS(SIGK_V_FWD)};
 #undef SIGK_V_FWD
-#define SIGK_V_BWD(P, D) {P, D, nullptr, nullptr, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_bwd_##P##_##D},
+#define SIGK_V_BWD(P, D) {P, D, nullptr, nullptr, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_ckpt_##P##_##D, occupancy_bwd_##P##_##D},
 const Variant kBwdTable[] = {SIGK_BWD_VARIANTS(SIGK_V_BWD)};
 #undef SIGK_V_BWD
 
@@ -63,37 +64,40 @@ const Variant* find_bwd(int P, int D) {
     return nullptr;
 }
 
-// resident workgroups per device for a variant (cached)
 std::mutex g_mu;
 struct OccKey {
-    int dev, P, D, bwd;
+    int dev, P, D, kind;
     int value;
 };
 std::vector<OccKey> g_occ;
 int g_cus[64] = {0};
 
-int device_wgs(int P, int D, bool bwd) {
+// resident workgroups per device for a variant's forward, adjoint or
+// checkpoint kernel (their register and LDS footprints differ)
+enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2 };
+
+int device_wgs(int P, int D, int kind) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& k : g_occ)
-        if (k.dev == dev && k.P == P && k.D == D && k.bwd == (int)bwd) return k.value;
+        if (k.dev == dev && k.P == P && k.D == D && k.kind == kind) return k.value;
     if (dev < 64 && g_cus[dev] == 0) {
         int cus = 0;
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         g_cus[dev] = cus;
     }
     int occ = 0;
-    if (bwd) {
-        const Variant* v = find_bwd(P, D);
-        occ = v ? v->occ_bwd() : 0;
-    } else {
+    if (kind == kKernelFwd) {
         const Variant* v = find_fwd(P, D);
         occ = v ? v->occ_fwd() : 0;
+    } else {
+        const Variant* v = find_bwd(P, D);
+        occ = v ? (kind == kKernelBwd ? v->occ_bwd() : v->occ_ckpt()) : 0;
     }
     if (occ < 1) occ = 1;
     int value = occ * (dev < 64 ? g_cus[dev] : 256);
-    g_occ.push_back({dev, P, D, (int)bwd, value});
+    g_occ.push_back({dev, P, D, kind, value});
     return value;
 }
 
@@ -263,7 +267,7 @@ int sigk_device_grid(int order, int64_t d, int backward) {
     const int D = round_dim(d);
     if (!P || !D) return 0;
     if (backward && !find_bwd(P, D)) return 0;
-    return device_wgs(P, D, backward != 0);
+    return device_wgs(P, D, backward != 0 ? kKernelBwd : kKernelFwd);
 }
 
 const char* sigk_strerror(int code) {
@@ -332,7 +336,7 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     a.ckpt = nullptr;
     const Variant* v = find_fwd(P, D);
     if (!v) return SIGK_EUNSUPPORTED;
-    int grid = op.grid > 0 ? op.grid : device_wgs(P, D, false);
+    int grid = op.grid > 0 ? op.grid : device_wgs(P, D, kKernelFwd);
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->fwd(a, std::max(grid, 1), s);
     if (e != hipSuccess) return device_error(e);
@@ -517,7 +521,7 @@ int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* 
     a.hdr = hdr;
     const Variant* v = find_fwd(plan->P, plan->D);
     if (!v) return SIGK_EUNSUPPORTED;
-    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, false);
+    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, kKernelFwd);
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->fwd(a, std::max(grid, 1), s);
     if (e != hipSuccess) return device_error(e);
@@ -606,7 +610,7 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     a.progress = prog;
     a.hdr = hdr;
     a.ckpt = (double*)(base + plan->o_ckpt);
-    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, false);
+    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, kKernelCkpt);
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->ckpt(a, std::max(grid, 1), s);
     if (e != hipSuccess) return device_error(e);
@@ -623,7 +627,7 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     b.lam_prog = lprog;
     b.gdx = gdx;
     b.scratch = (double*)(base + plan->o_scr);
-    int bgrid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, true);
+    int bgrid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, kKernelBwd);
     bgrid = (int)std::min<int64_t>(std::min(bgrid, plan->bwd_grid), b.ntickets);
     e = v->bwd(b, std::max(bgrid, 1), s);
     if (e != hipSuccess) return device_error(e);

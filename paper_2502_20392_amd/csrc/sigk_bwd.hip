@@ -412,6 +412,14 @@ hipError_t SIGK_NAME(launch_bwd_, SIGK_P, SIGK_D)(const BwdArgs& b, int grid, hi
     return hipGetLastError();
 }
 
+int SIGK_NAME(occupancy_ckpt_, SIGK_P, SIGK_D)() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ckpt_kernel<SIGK_P, SIGK_D>, kWave, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
 int SIGK_NAME(occupancy_bwd_, SIGK_P, SIGK_D)() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bwd_kernel<SIGK_P, SIGK_D>, kWave, 0) !=

@@ -120,6 +120,7 @@ SIGK_FWD_VARIANTS(SIGK_DECL_FWD)
 #define SIGK_DECL_BWD(P, D) \
     hipError_t launch_ckpt_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
     hipError_t launch_bwd_##P##_##D(const BwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_ckpt_##P##_##D(); \
     int occupancy_bwd_##P##_##D();
 SIGK_BWD_VARIANTS(SIGK_DECL_BWD)
 #undef SIGK_DECL_BWD
