@@ -441,13 +441,13 @@ struct StripCtx {
     // depth is dispatched to a loop specialised for it (no branch per term).
     template <int QD>
     __device__ __forceinline__ void run_depth(int& t, int te) {
-        if constexpr (P <= 8 && QD < P - 1) {
+        if constexpr (P <= 12 && QD < P - 1) {
             if (q > QD) {
                 run_depth<QD + 1>(t, te);
                 return;
             }
         }
-        constexpr int QC = P <= 8 ? QD : -1;
+        constexpr int QC = P <= 12 ? QD : -1;
         for (; t < te; ++t) {
             if (ck && ((unsigned)t % (unsigned)ck_every) == 0) save_state(t);
             step<false, QC>(t, lane_ok);
