@@ -372,30 +372,39 @@ struct StripCtx {
         const int col = t - lane;
         double A[P];
         const double* bsrc = &L.bin[((unsigned)t % (unsigned)CH) * P];  // t >= 0
-        if constexpr (kAhead && !EDGE && QC >= 0) {
+        if constexpr (!EDGE && QC >= 0) {
             // steady state, depth known at compile time: B-only work first
             double bv[P];
             lds_copy<P>(bv, bsrc);
-            // increments of the next step's column, consumed after the map
-            const int ri = ring_slot<P>(t + 1 - lane);
-            double dxv[D];
+            double c;
+            double dxv[kAhead ? D : 1];
+            if constexpr (kAhead) {
+                // increments of the next step's column, consumed after the map
+                c = cn;
+                const int ri = ring_slot<P>(t + 1 - lane);
 #pragma unroll
-            for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * ring_cols(P) + ri];
+                for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * ring_cols(P) + ri];
+            } else {
+                prefetch(t);
+                c = cn;
+            }
             double An[P], Bn[P];
             SplitMap<P, QC> S;
-            S.pre(B, cn, Bn, R);
+            S.pre(B, c, Bn, R);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bv[i]);
             S.post(A, An, Bn, R);
-            __builtin_amdgcn_sched_barrier(0);
-            double c0 = 0.0, c1 = 0.0;
+            if constexpr (kAhead) {
+                __builtin_amdgcn_sched_barrier(0);
+                double c0 = 0.0, c1 = 0.0;
 #pragma unroll
-            for (int ch = 0; ch < D; ch += 2) {
-                c0 = fma(dy[ch], dxv[ch], c0);
-                c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
+                for (int ch = 0; ch < D; ch += 2) {
+                    c0 = fma(dy[ch], dxv[ch], c0);
+                    c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
+                }
+                cn = c0 + c1;
             }
-            cn = c0 + c1;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 B[i] = Bn[i];
