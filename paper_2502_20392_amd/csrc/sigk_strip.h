@@ -372,7 +372,7 @@ struct StripCtx {
         const int col = t - lane;
         double A[P];
         const double* bsrc = &L.bin[((unsigned)t % (unsigned)CH) * P];  // t >= 0
-        if constexpr (!EDGE && QC >= 0) {
+        if constexpr (!EDGE && QC >= 0 && P <= 12) {
             // steady state, depth known at compile time: B-only work first
             double bv[P];
             lds_copy<P>(bv, bsrc);
@@ -450,13 +450,13 @@ struct StripCtx {
     // depth is dispatched to a loop specialised for it (no branch per term).
     template <int QD>
     __device__ __forceinline__ void run_depth(int& t, int te) {
-        if constexpr (P <= 12 && QD < P - 1) {
+        if constexpr (QD < P - 1) {
             if (q > QD) {
                 run_depth<QD + 1>(t, te);
                 return;
             }
         }
-        constexpr int QC = P <= 12 ? QD : -1;
+        constexpr int QC = QD;
         for (; t < te; ++t) {
             if (ck && ((unsigned)t % (unsigned)ck_every) == 0) save_state(t);
             step<false, QC>(t, lane_ok);
