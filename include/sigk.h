@@ -169,6 +169,23 @@ int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths,
  */
 int sigk_plan_backward(const sigk_plan* plan, const double* pool, const double* grad_out,
                        double* grad_pool, void* ws, size_t ws_bytes, void* stream);
+/*
+ * The two halves of sigk_plan_backward, for callers that need the kernel
+ * values before the gradient (an autograd forward pass):
+ * sigk_plan_run_checkpointed computes out[p] = k(pair p) like sigk_plan_run
+ * by the checkpointing forward sweep, leaving its checkpoints in ws (backward
+ * workspace size; the plan must have been uploaded into ws);
+ * sigk_plan_backward_checkpointed then accumulates the gradient of
+ * sum_p grad_out[p] k_p into grad_pool from those checkpoints, without
+ * recomputing the forward.  The pool must be unchanged in between and ws not
+ * used for any other call; the adjoint may be run several times (different
+ * grad_out) on one set of checkpoints.
+ */
+int sigk_plan_run_checkpointed(const sigk_plan* plan, const double* pool, double* out, void* ws,
+                               size_t ws_bytes, void* stream);
+int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
+                                    const double* grad_out, double* grad_pool, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- status */
 /* Synchronous: waits for stream, reads counters and the status word of ws. */

@@ -75,6 +75,8 @@ SIGNATURES = {
     "sigk_gram_ragged": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(Opts), _P,
                                         _P, _SZ, _P]),
     "sigk_plan_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
+    "sigk_plan_run_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
+    "sigk_plan_backward_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
     "sigk_read_counters": (ctypes.c_int, [_P, ctypes.POINTER(Counters), _P]),
     "sigk_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), _P]),
 }

@@ -203,16 +203,30 @@ class RaggedPlan:
             self.run(pool, out)
         return g
 
-    def backward(self, pool, grad_out, grad_pool=None):
-        """grad_pool += d(sum_p grad_out[p] k_p)/d pool."""
+    def run_checkpointed(self, pool, out=None):
+        """As ``run``, by the checkpointing forward sweep: the checkpoints stay in
+        the plan's workspace for ``backward(..., checkpointed=True)``."""
+        pool = _check_paths(pool, "pool", 2)
+        ws = self.ensure_workspace(backward=True)
+        if out is None:
+            out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
+        _lib.check(_lib.load().sigk_plan_run_checkpointed(self._h, _ptr(pool), _ptr(out),
+                                                          _ptr(ws), ws.numel(), _stream()))
+        _tls.ws = ws
+        return out
+
+    def backward(self, pool, grad_out, grad_pool=None, checkpointed=False):
+        """grad_pool += d(sum_p grad_out[p] k_p)/d pool.  checkpointed: reuse the
+        checkpoints of the last ``run_checkpointed`` on the same pool."""
         pool = _check_paths(pool, "pool", 2)
         grad_out = grad_out.contiguous().to(torch.float64)
         ws = self.ensure_workspace(backward=True)
         if grad_pool is None:
             grad_pool = torch.zeros_like(pool)
-        _lib.check(_lib.load().sigk_plan_backward(self._h, _ptr(pool), _ptr(grad_out),
-                                                  _ptr(grad_pool), _ptr(ws), ws.numel(),
-                                                  _stream()))
+        fn = (_lib.load().sigk_plan_backward_checkpointed if checkpointed
+              else _lib.load().sigk_plan_backward)
+        _lib.check(fn(self._h, _ptr(pool), _ptr(grad_out), _ptr(grad_pool), _ptr(ws), ws.numel(),
+                      _stream()))
         _tls.ws = ws
         return grad_pool
 
@@ -257,7 +271,11 @@ class _GramFunction(torch.autograd.Function):
     def forward(ctx, X, Y, order, tol, symmetric):
         pool, offsets, pairs = _pool_and_pairs(X, Y, symmetric)
         plan = RaggedPlan(offsets, pairs, X.shape[2], order=order, tol=tol, device=X.device)
-        vals = plan.run(pool)
+        grad = X.requires_grad or (Y is not None and Y.requires_grad)
+        # with a gradient ahead, the checkpointing sweep gives the values and
+        # the checkpoints the adjoint needs (no second forward in backward)
+        vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
+        ctx.checkpointed = grad
         nx = X.shape[0]
         ny = nx if symmetric else Y.shape[0]
         G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
@@ -282,7 +300,7 @@ class _GramFunction(torch.autograd.Function):
             w = torch.where(ii == jj, gG[ii, jj], w)
         else:
             w = gG.reshape(-1)
-        gpool = ctx.plan.backward(ctx.pool, w.contiguous())
+        gpool = ctx.plan.backward(ctx.pool, w.contiguous(), checkpointed=ctx.checkpointed)
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gX = gpool[:nxp].reshape(xs)
@@ -300,10 +318,12 @@ def sigkernel_gram(X, Y=None, order=12, tol=None):
 
 
 class _MMD2Function(torch.autograd.Function):
-    """Biased MMD^2 = mean k(X,X) + mean k(Y,Y) - 2 mean k(X,Y) in one ragged launch.
+    """Biased MMD^2 = mean k(X,X) + mean k(Y,Y) - 2 mean k(X,Y).
 
-    The backward runs the adjoint only over the pairs that involve an input
-    that needs a gradient (XX and XY for dMMD^2/dX)."""
+    When an input needs a gradient, the blocks that involve it (XX and XY for
+    dMMD^2/dX) are evaluated by the checkpointing forward sweep, whose
+    checkpoints the backward's adjoint then uses directly; the other block
+    runs in a plain forward launch."""
 
     @staticmethod
     def forward(ctx, X, Y, order, tol):
@@ -320,24 +340,33 @@ class _MMD2Function(torch.autograd.Function):
         weights = [np.where(xi == xj, 1.0, 2.0) / (nx * nx),
                    np.where(yi == yj, 1.0, 2.0) / (ny * ny),
                    np.full(nx * ny, -2.0 / (nx * ny))]
-        pairs = np.concatenate(blocks).astype(np.int32)
-        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
-        vals = plan.run(pool)
-        wt = torch.from_numpy(np.concatenate(weights)).to(X.device)
-        ctx.save = (offsets, blocks, weights, d, order, tol)
+        need_x, need_y = X.requires_grad, Y.requires_grad
+        use = [need_x, need_y, need_x or need_y]  # XX, YY, XY blocks with a gradient
+        total = torch.zeros((), dtype=torch.float64, device=X.device)
+        plan_g = None
+        for grad in (True, False):
+            sel = [u == grad for u in use]
+            if not any(sel):
+                continue
+            pairs = np.concatenate([b for b, u in zip(blocks, sel) if u]).astype(np.int32)
+            w = np.concatenate([x for x, u in zip(weights, sel) if u])
+            plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
+            vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
+            wt = torch.from_numpy(w).to(X.device)
+            total = total + (vals * wt).sum()
+            if grad:
+                plan_g, w_g = plan, wt
+        ctx.plan = plan_g
+        ctx.w = w_g if plan_g is not None else None
         ctx.pool, ctx.shapes = pool, (X.shape, Y.shape)
-        return (vals * wt).sum()
+        return total
 
     @staticmethod
     def backward(ctx, g):
-        offsets, blocks, weights, d, order, tol = ctx.save
         need_x, need_y = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        use = [need_x, need_y, need_x or need_y]  # XX, YY, XY blocks
-        pairs = np.concatenate([b for b, u in zip(blocks, use) if u]).astype(np.int32)
-        w = np.concatenate([x for x, u in zip(weights, use) if u])
-        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=ctx.pool.device)
-        wt = torch.from_numpy(w).to(ctx.pool.device) * g
-        gpool = plan.backward(ctx.pool, wt.contiguous())
+        if ctx.plan is None or not (need_x or need_y):
+            return None, None, None, None
+        gpool = ctx.plan.backward(ctx.pool, (ctx.w * g).contiguous(), checkpointed=True)
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gx = gpool[:nxp].reshape(xs) if need_x else None

@@ -442,6 +442,10 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
 
 namespace {
 
+// Adjoint ticket counter (the adjoint may run long after the checkpoint pass
+// that reset the header).
+__global__ void zero_tickets_kernel(WsHeader* h) { h->ticket2 = 0; }
+
 __global__ void zero_kernel(int* ip, int64_t ni, double* dp, int64_t nd) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -573,28 +577,18 @@ int sigk_read_status(const void* ws, uint32_t* status_bits, void* stream) {
 
 }  // extern "C"
 
-extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
-                                  const double* grad_out, double* grad_pool, void* ws,
-                                  size_t ws_bytes, void* stream) {
-    if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
-        return SIGK_EINVAL;
-    if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
-    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
-    const Variant* v = find_bwd(plan->P, plan->D);
-    if (!v) return SIGK_EUNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
+namespace {
+
+// Checkpoint pass: the forward sweep of every strip (64-row strips), keeping
+// the frontier row each strip reads, the wave state every kCkptEvery steps and
+// the depth of every chunk; writes the kernel values to out when out != null.
+int checkpoint_pass(const sigk_plan* plan, const Variant* v, const double* pool, double* out,
+                    char* base, hipStream_t s) {
     WsHeader* hdr = (WsHeader*)base;
     int* prog = (int*)(base + plan->o_prog);
-    int* lprog = (int*)(base + plan->o_lprog);
-    double* gdx = (double*)(base + plan->o_gdx);
-    const int64_t ngdx = plan->pool_points * plan->d;
-    hipError_t e = launch_reset(hdr, prog, plan->nprog, nullptr, 0, (unsigned)plan->P, s);
+    hipError_t e = launch_reset(hdr, prog, plan->nprog, out, out ? plan->npairs : 0,
+                                (unsigned)plan->P, s);
     if (e != hipSuccess) return device_error(e);
-    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(std::max(plan->nprog, ngdx))), dim3(256), 0,
-                       s, lprog, plan->nprog, gdx, ngdx);
-    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
-    // checkpointing forward pass
     FwdArgs a;
     std::memset(&a, 0, sizeof a);
     fill_common(a, plan->opts, plan->P, plan->d, plan->max_cells);
@@ -605,7 +599,7 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     a.ntickets = (int64_t)plan->tickets.size();
     a.desc = (const PairDesc*)(base + plan->o_desc);
     a.tickets = (const Ticket*)(base + plan->o_tk);
-    a.out = nullptr;
+    a.out = out;
     a.frontier = (double*)(base + plan->o_snap);
     a.progress = prog;
     a.hdr = hdr;
@@ -614,10 +608,31 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->ckpt(a, std::max(grid, 1), s);
     if (e != hipSuccess) return device_error(e);
-    // adjoint sweep
+    return SIGK_OK;
+}
+
+// Adjoint pass over the checkpoints in base, then the chain to the points.
+int adjoint_pass(const sigk_plan* plan, const Variant* v, const double* pool,
+                 const double* grad_out, double* grad_pool, char* base, hipStream_t s) {
+    WsHeader* hdr = (WsHeader*)base;
+    int* lprog = (int*)(base + plan->o_lprog);
+    double* gdx = (double*)(base + plan->o_gdx);
+    const int64_t ngdx = plan->pool_points * plan->d;
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(std::max(plan->nprog, ngdx))), dim3(256), 0,
+                       s, lprog, plan->nprog, gdx, ngdx);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    hipLaunchKernelGGL(zero_tickets_kernel, dim3(1), dim3(1), 0, s, hdr);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
     BwdArgs b;
     std::memset(&b, 0, sizeof b);
-    b.f = a;
+    fill_common(b.f, plan->opts, plan->P, plan->d, plan->max_cells);
+    b.f.mode = kModeTable;
+    b.f.X = pool;
+    b.f.Y = pool;
+    b.f.npairs = plan->npairs;
+    b.f.desc = (const PairDesc*)(base + plan->o_desc);
+    b.f.hdr = hdr;
     b.tickets = (const Ticket*)(base + plan->o_tkr);
     b.ntickets = (int64_t)plan->tickets_rev.size();
     b.grad_out = grad_out;
@@ -636,3 +651,51 @@ extern "C" int sigk_plan_backward(const sigk_plan* plan, const double* pool,
     if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
     return SIGK_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int sigk_plan_run_checkpointed(const sigk_plan* plan, const double* pool, double* out, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!plan || !ws || (plan->npairs > 0 && (!pool || !out))) return SIGK_EINVAL;
+    if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
+    if (plan->npairs == 0) return SIGK_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->tickets.empty()) {
+        hipError_t e = launch_reset((WsHeader*)ws, (int*)((char*)ws + plan->o_prog), plan->nprog,
+                                    out, plan->npairs, (unsigned)plan->P, s);
+        return e == hipSuccess ? SIGK_OK : device_error(e);
+    }
+    const Variant* v = find_bwd(plan->P, plan->D);
+    if (!v) return SIGK_EUNSUPPORTED;
+    return checkpoint_pass(plan, v, pool, out, (char*)ws, s);
+}
+
+int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
+                                    const double* grad_out, double* grad_pool, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
+        return SIGK_EINVAL;
+    if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
+    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
+    const Variant* v = find_bwd(plan->P, plan->D);
+    if (!v) return SIGK_EUNSUPPORTED;
+    return adjoint_pass(plan, v, pool, grad_out, grad_pool, (char*)ws, (hipStream_t)stream);
+}
+
+int sigk_plan_backward(const sigk_plan* plan, const double* pool, const double* grad_out,
+                       double* grad_pool, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
+        return SIGK_EINVAL;
+    if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
+    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
+    const Variant* v = find_bwd(plan->P, plan->D);
+    if (!v) return SIGK_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = checkpoint_pass(plan, v, pool, nullptr, (char*)ws, s);
+    if (rc) return rc;
+    return adjoint_pass(plan, v, pool, grad_out, grad_pool, (char*)ws, s);
+}
+
+}  // extern "C"

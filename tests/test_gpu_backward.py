@@ -186,3 +186,61 @@ def test_rough_gradient(dev, order):
     assert np.abs(gx - gx0).max() <= 1e-8 * sc
     assert np.abs(gy - gy0).max() <= 1e-8 * sc
     assert sk().counters()["status"] == 0
+
+
+def test_checkpointed_entry_points(dev):
+    """sigk_plan_run_checkpointed gives the values of sigk_plan_run; the adjoint
+    from its checkpoints (run twice on them) equals sigk_plan_backward and the
+    oracle's gradient."""
+    pool, off, _ = synth.ragged_paths(n_paths=6, lmin=30, lmax=150, d=5, smin=0.3, smax=0.6)
+    pairs = np.array([[0, 1], [2, 3], [4, 5], [1, 4], [3, 3]], dtype=np.int32)
+    w = synth.rng(4400).normal(size=len(pairs))
+    plan = sk().RaggedPlan(off, pairs, 5, order=12, device=dev)
+    pd = T(pool, dev)
+    v_run = plan.run(pd).cpu().numpy()
+    v_ck = plan.run_checkpointed(pd).cpu().numpy()
+    np.testing.assert_array_equal(v_ck, v_run)
+    g1 = plan.backward(pd, T(w, dev), checkpointed=True).cpu().numpy()
+    g2 = plan.backward(pd, T(w, dev), checkpointed=True).cpu().numpy()
+    g3 = plan.backward(pd, T(w, dev)).cpu().numpy()
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(g1, g3)
+    ref = np.zeros_like(pool)
+    for (a, b), wi in zip(pairs, w):
+        xa, xb = pool[off[a]:off[a + 1]], pool[off[b]:off[b + 1]]
+        _, ga, gb = oracle.grad(xa, xb)
+        ref[off[a]:off[a + 1]] += wi * ga
+        ref[off[b]:off[b + 1]] += wi * gb
+    assert np.abs(g1 - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    assert sk().counters(plan.ws)["status"] == 0
+
+
+def test_mmd_gradient_wrt_y_and_both(dev):
+    """MMD^2 with the gradient taken for Y only and for both sets: the blocks
+    that involve a differentiated set run checkpointed, the rest plainly."""
+    X, Y = synth.mmd_sets(n=3, length=96)
+    ref_x = np.zeros_like(X)
+    ref_y = np.zeros_like(Y)
+    n = 3
+    for i in range(n):
+        for j in range(n):
+            _, gi, gj = oracle.grad(X[i], X[j])
+            ref_x[i] += gi / n ** 2
+            ref_x[j] += gj / n ** 2
+            _, gi, gj = oracle.grad(Y[i], Y[j])
+            ref_y[i] += gi / n ** 2
+            ref_y[j] += gj / n ** 2
+            _, gi, gj = oracle.grad(X[i], Y[j])
+            ref_x[i] += -2 * gi / n ** 2
+            ref_y[j] += -2 * gj / n ** 2
+    sc = max(1.0, np.abs(ref_x).max(), np.abs(ref_y).max())
+    Yt = T(Y, dev).requires_grad_(True)
+    sk().mmd2(T(X, dev), Yt, order=10).backward()
+    assert np.abs(Yt.grad.cpu().numpy() - ref_y).max() <= 1e-10 * sc
+    Xt = T(X, dev).requires_grad_(True)
+    Yt = T(Y, dev).requires_grad_(True)
+    m = sk().mmd2(Xt, Yt, order=10)
+    m.backward()
+    assert abs(m.item() - mmd2_oracle(X, Y)) <= 1e-12
+    assert np.abs(Xt.grad.cpu().numpy() - ref_x).max() <= 1e-10 * sc
+    assert np.abs(Yt.grad.cpu().numpy() - ref_y).max() <= 1e-10 * sc
