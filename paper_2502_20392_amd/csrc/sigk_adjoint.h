@@ -27,8 +27,8 @@
 namespace sigk {
 
 // Powers e_n = c^n/n!, n = N..q (e[0] = 1).
-template <int P, int N>
-__device__ __forceinline__ void powers(double c, int q, double (&e)[P], const Recip<P>& R) {
+template <int P, int N, class RC>
+__device__ __forceinline__ void powers(double c, int q, double (&e)[P], const RC& R) {
     if constexpr (N < P) {
         if (N > q) return;
         e[N] = e[N - 1] * c * R(N);
@@ -38,9 +38,9 @@ __device__ __forceinline__ void powers(double c, int q, double (&e)[P], const Re
 
 // Hankel sums of one edge, h_n = sum_{r>=1} V_r n!/(n+r)!, n = N..q (Horner
 // form, as in the forward map).
-template <int P, int N>
+template <int P, int N, class RC>
 __device__ __forceinline__ void hankel_sum(const double (&V)[P], int q, double (&h)[P],
-                                           const Recip<P>& R) {
+                                           const RC& R) {
     if constexpr (N < P) {
         if (N > q) return;
         double t = V[P - 1];
@@ -72,12 +72,12 @@ __device__ __forceinline__ void unmap_left(const double (&A)[P], double (&B)[P],
 
 // Term N >= 1 of the adjoint: Toeplitz transposes, Hankel transposes and the
 // dL/dc contribution.  e = e_{N-1} on entry.
-template <int P, int N>
+template <int P, int N, class RC>
 __device__ __forceinline__ void adjoint_terms(const double (&A)[P], const double (&B)[P],
                                               double c, double e, int q, const double (&hA)[P],
                                               const double (&hB)[P], const double (&lAo)[P],
                                               const double (&lBo)[P], double (&lA)[P],
-                                              double (&lB)[P], double& g, const Recip<P>& R) {
+                                              double (&lB)[P], double& g, const RC& R) {
     if constexpr (N < P) {
         if (N > q) return;
         const double ep = e;             // e_{N-1} = d e_N / dc
@@ -115,12 +115,12 @@ __device__ __forceinline__ void adjoint_terms(const double (&A)[P], const double
 // cotangents lA, lB and returns dL/dc.  The recovered left edge differs from
 // the forward one by rounding only; it enters dL/dc, never the cotangents
 // (those depend on c alone).
-template <int P>
+template <int P, class RC>
 __device__ __forceinline__ double cell_adjoint(const double (&A)[P], double (&B)[P], double c,
                                                int q, bool boundary, bool live,
                                                const double (&lAo)[P],
                                                const double (&lBo)[P], double (&lA)[P],
-                                               double (&lB)[P], const Recip<P>& R) {
+                                               double (&lB)[P], const RC& R) {
     double e[P], hA[P], hB[P];
     e[0] = 1.0;
     powers<P, 1>(c, q, e, R);
@@ -163,12 +163,12 @@ __device__ __forceinline__ double cell_adjoint(const double (&A)[P], double (&B)
 //     sum_{n=1}^{Q} e_n lA'_n n!/(n+r)!
 //         = (1/(r+1)!) [u_1 + (1/(r+2)) [u_2 + ... + (1/(Q+r)) u_Q]],
 // with u_n = c^n lA'_n: one FMA per (n, r) instead of a multiply and an add.
-template <int P, int Q>
+template <int P, int Q, class RC>
 __device__ __forceinline__ double cell_adjoint_fixed(const double (&A)[P], double (&B)[P],
                                                      double c, bool boundary, bool live,
                                                      const double (&lAo)[P],
                                                      const double (&lBo)[P], double (&lA)[P],
-                                                     double (&lB)[P], const Recip<P>& R) {
+                                                     double (&lB)[P], const RC& R) {
     double e[Q + 1], cp[Q + 1], hA[Q + 1], hB[Q + 1];
     e[0] = 1.0;
     cp[0] = 1.0;

@@ -79,7 +79,7 @@ struct StripBwd {
     const PairDesc* pd;
     double dy[D];
     double gy[D];
-    Recip<P> R;
+    Recip<P, false> R;  // scalar or rematerialised constants: registers are scarce here
     int dx_lo, lin_lo, bin_chunk;
     double* scratch;
     const double* ck;

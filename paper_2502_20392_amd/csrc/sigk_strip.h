@@ -59,14 +59,14 @@ struct Acc {
 // in vector registers (the wave runs alone on its SIMD there anyway), so the
 // hot loop neither rebuilds them nor spills them from scalar registers; for
 // small P the registers buy more occupancy instead.
-template <int P>
+template <int P, bool kPinVector = (P >= 10 && P <= 12)>
 struct Recip {
     double v[2 * P + 1];
     __device__ __forceinline__ void init() {
 #pragma unroll
         for (int k = 0; k <= 2 * P; ++k) {
             v[k] = k == 0 ? 0.0 : 1.0 / (double)k;
-            if (P >= 10 && P <= 12) asm volatile("" : "+v"(v[k]));
+            if (kPinVector) asm volatile("" : "+v"(v[k]));
             else if (P <= 8 && k > 2) asm volatile("" : "+s"(v[k]));
         }
     }
@@ -90,10 +90,10 @@ __host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
 // term (1 for N = 1), so e_N = ep c and e_N/(N+1) = e_N (1/(N+1)).  Written
 // as a compile-time recursion so that every coefficient index is a constant
 // (registers, never scratch).
-template <int P, int N>
+template <int P, int N, class RC>
 __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double (&B)[P],
                                               double c, double ep, double (&An)[P],
-                                              double (&Bn)[P], int q, const Recip<P>& R) {
+                                              double (&Bn)[P], int q, const RC& R) {
     if constexpr (N < P) {
         if (N > q) return;  // scalar, uniform (folds away for a constant q)
         const double e = N == 1 ? c : ep * c;
@@ -117,10 +117,10 @@ __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double
 }
 
 // The truncated cell map with Neumann depth q (wave-uniform, q <= P-1).
-template <int P>
+template <int P, class RC>
 __device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], double c,
                                          double (&An)[P], double (&Bn)[P], int q,
-                                         const Recip<P>& R) {
+                                         const RC& R) {
     B[0] = A[0];
     // n = 0: corner values from the edges, sum_{r>=1} B_r/r! and sum A_r/r!
     {
@@ -151,8 +151,9 @@ template <int P, int Q>
 struct SplitMap {
     double e[Q + 1], en[Q + 1], tb[Q + 1];
 
+    template <class RC>
     __device__ __forceinline__ void pre(const double (&B)[P], double c, double (&Bn)[P],
-                                        const Recip<P>& R) {
+                                        const RC& R) {
 #pragma unroll
         for (int n = 0; n <= Q; ++n) {
             if (n > 0) {
@@ -172,8 +173,9 @@ struct SplitMap {
             for (int i = n + 1; i < P; ++i) Bn[i] = fma(e[n], B[i - n], Bn[i]);
     }
 
+    template <class RC>
     __device__ __forceinline__ void post(const double (&A)[P], double (&An)[P], double (&Bn)[P],
-                                         const Recip<P>& R) {
+                                         const RC& R) {
 #pragma unroll
         for (int i = 1; i < P; ++i) An[i] = A[i];
 #pragma unroll
