@@ -118,10 +118,16 @@ struct StripBwd {
         while (lin_lo > lo_needed && lin_lo > 0) {
             const int c0 = lin_lo - CH;
             const int nc = min(CH, m - c0);
-            if (!wait_at_least(&lam_prog[s + 1], m - c0, a.hdr, a.watchdog_ticks)) return false;
+            if (!wait_flag(&lam_prog[s + 1], m - c0, a.hdr, a.watchdog_ticks)) return false;
             double* dst = &L.lin[((c0 / CH) & 1) * CH * P];
-            const double* src = lam_row + (int64_t)c0 * P;
-            for (int e = lane; e < nc * P; e += kWave) dst[e] = src[e];
+            constexpr int NB = (chunk_cols(P) * P + kWave - 1) / kWave;
+            const CoherentSpan src(lam_row + (int64_t)c0 * P, nc * P);
+            double v[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) v[k] = src.load(lane + k * kWave);
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (lane + k * kWave < nc * P) dst[lane + k * kWave] = v[k];
             lin_lo = c0;
             __syncthreads();
         }
@@ -152,8 +158,8 @@ struct StripBwd {
         const int nc = c1 - c0;
         if (has_below) {
             double* dst = lam_row + (int64_t)c0 * P;
-            for (int e = lane; e < nc * P; e += kWave) dst[e] = L.lout[e];
-            publish(&lam_prog[s], m - c0);
+            for (int e = lane; e < nc * P; e += kWave) store_coherent(&dst[e], L.lout[e]);
+            publish_coherent(&lam_prog[s], m - c0);
         }
         if (lane < nc) {
             const int col = c0 + lane;

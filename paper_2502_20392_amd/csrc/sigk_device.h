@@ -8,13 +8,6 @@
 
 namespace sigk {
 
-// ---------------------------------------------------------------- constants
-// 1/i!
-__host__ __device__ constexpr double ifact(int i) {
-    double v = 1.0;
-    for (int q = 2; q <= i; ++q) v /= (double)q;
-    return v;
-}
 // ---------------------------------------------------------------- lanes
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
 
@@ -54,46 +47,15 @@ __device__ __forceinline__ void raise_status(WsHeader* h, unsigned bits) {
         __hip_atomic_fetch_or(&h->status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until *flag >= need.  Returns false (and raises the watchdog bit for
-// everyone) if the wait exceeds `ticks` of the 100 MHz real-time counter, or
-// if another wave already raised it.
-__device__ bool wait_at_least(const int* flag, int need, WsHeader* h, long long ticks) {
-    int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (uniform(v) < need) {
-        const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
-        for (;;) {
-            __builtin_amdgcn_s_sleep(2);
-            v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (uniform(v) >= need) break;
-            if (uniform((int)(load_status(h) & SIGK_ERR_WATCHDOG))) return false;
-            const long long now = (long long)__builtin_amdgcn_s_memrealtime();
-            if (now - t0 > ticks) {
-                raise_status(h, SIGK_ERR_WATCHDOG);
-                return false;
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
-}
-
-__device__ __forceinline__ void publish(int* flag, int value) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane_id() == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Device-coherent accesses for data exchanged between workgroups without
 // cache maintenance: the producer writes with device-scope stores (written
 // through to the level shared by all XCDs), waits for them to complete and
 // then raises a flag; the consumer polls the flag and reads the data with
-// device-scope loads.  No L2 write-back or invalidation is needed.
+// device-scope loads (CoherentSpan).  No L2 write-back or invalidation is
+// needed.
 __device__ __forceinline__ void store_coherent(double* p, double v) {
     __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_coherent(const double* p) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 // n doubles at p read with device-coherent plain loads (buffer loads with the
@@ -118,8 +80,11 @@ struct CoherentSpan {
     static constexpr int kCoherentLoad = 16;  // cache-policy operand: sc1
 };
 
-// As wait_at_least, for data read back with load_coherent: no cache
-// invalidation, only ordering of the following loads after the flag.
+// Wait until *flag >= need, for data then read back with device-coherent
+// loads (no cache invalidation, only ordering of the following loads after
+// the flag).  Returns false (and raises the watchdog bit for everyone) if the
+// wait exceeds `ticks` of the 100 MHz real-time counter, or if another wave
+// already raised it.
 __device__ bool wait_flag(const int* flag, int need, WsHeader* h, long long ticks) {
     int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (uniform(v) < need) {

@@ -259,7 +259,6 @@ struct StripCtx {
     double dymax2;      // max_l |dy_l|^2 over the strip
     int q;              // Neumann depth of the current chunk
     unsigned nvalid;
-    uint64_t okmask;    // lanes holding a grid row
     Recip<P> R;
     // checkpointing (adjoint support)
     double* ck;         // wave-state checkpoints of this strip or null
@@ -527,7 +526,6 @@ struct StripCtx {
         has_below = s > 0;
         has_above = row0 + kWave < g.n;
         nvalid = (unsigned)nrows;
-        okmask = ballot(lane_ok);
         R.init();
         const int l = row0 + lane;
         double n2 = 0.0;
