@@ -8,8 +8,10 @@
 // top-edge series it produces moves to lane j+1 for the next step by a DPP
 // wave shift.  Lane 0 takes its bottom edge from the frontier row written by
 // the strip below; lane 63 writes its top edge to the frontier for the strip
-// above.  Frontier columns are exchanged between strips in chunks through
-// LDS with one release/acquire progress counter per strip.
+// above.  Frontier columns are exchanged between strips in chunks of 32:
+// lane 63's edges are staged in LDS and written out with device-coherent
+// stores, followed by a progress flag per strip; the strip above polls the
+// flag and reads the chunk with device-coherent loads (no cache maintenance).
 //
 // Cell map (Prop. 2.8 in the derivative basis).  With A the bottom-edge and B
 // the left-edge series in unit-cell coordinates, f(u) = sum_i A_i u^i / i!,
@@ -23,7 +25,7 @@
 // Neumann depth.  Term n (the entries of C with min(i, j) = n, the n-th term
 // of the series of Prop. 2.5) is bounded by |c|^n/(n!)^2 relative to the edge
 // data.  It is applied while |c| may exceed tau_n = (tol (n!)^2)^(1/n)
-// anywhere in the cells a chunk of 64 steps covers, using the exact bound
+// anywhere in the cells a chunk of 32 steps covers, using the exact bound
 // |c| = |<dx_k, dy_l>| <= |dx_k| |dy_l| (Cauchy-Schwarz).  The depth is
 // therefore uniform over the wave and known before each chunk, so the step
 // loop carries no data-dependent branch.
