@@ -24,7 +24,7 @@ ERR_WATCHDOG = 4
 FLAG_FIXED_DEPTH = 1
 
 ORDERS = (4, 5, 6, 8, 10, 12, 16, 20, 24)
-BWD_ORDERS = (4, 5, 6, 8, 10, 12, 16)
+BWD_ORDERS = (4, 5, 6, 8, 10, 12, 16, 20, 24)
 
 
 class SigkError(RuntimeError):

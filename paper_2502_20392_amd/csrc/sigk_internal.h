@@ -18,9 +18,9 @@ constexpr int kMaxP = 24;   // largest compiled edge order
 
 // Variants of the adjoint kernels.
 #define SIGK_BWD_VARIANTS(X) \
-    X(4, 8) X(5, 8) X(6, 8) X(8, 8) X(10, 8) X(12, 8) X(16, 8) \
-    X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) \
-    X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32)
+    X(4, 8) X(5, 8) X(6, 8) X(8, 8) X(10, 8) X(12, 8) X(16, 8) X(20, 8) X(24, 8) \
+    X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) X(20, 16) X(24, 16) \
+    X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32) X(20, 32) X(24, 32)
 
 // Frontier chunk (columns per progress flag) for edge order P.
 __host__ __device__ constexpr int chunk_cols(int P) { return 32; }
