@@ -156,6 +156,10 @@ int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* 
 int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
                      const int32_t* pairs, int64_t npairs, const sigk_opts* o, double* out,
                      void* ws, size_t ws_bytes, void* stream);
+/* Workspace bytes for sigk_gram_ragged (host; host offsets and pairs). */
+int sigk_gram_ragged_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
+                                    const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+                                    size_t* bytes);
 
 /* ---------------------------------------------------------------- adjoint */
 /*
@@ -186,6 +190,21 @@ int sigk_plan_run_checkpointed(const sigk_plan* plan, const double* pool, double
 int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
                                     const double* grad_out, double* grad_pool, void* ws,
                                     size_t ws_bytes, void* stream);
+
+/*
+ * Convenience: plan + upload + sigk_plan_backward in one call for a ragged
+ * batch (the gradient of L = sum_p grad_out[p] k(pair p) with respect to the
+ * pool, ACCUMULATED into grad_pool).  offsets and pairs are host arrays as for
+ * sigk_plan_ragged; synchronous with respect to the host (the plan's tables
+ * are copied from host memory); not capturable.  ws: at least
+ * sigk_backward_workspace_size bytes.
+ */
+int sigk_backward_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
+                                 const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+                                 size_t* bytes);
+int sigk_backward(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
+                  const int32_t* pairs, int64_t npairs, const double* grad_out, const sigk_opts* o,
+                  double* grad_pool, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- status */
 /* Synchronous: waits for stream, reads counters and the status word of ws. */

@@ -74,6 +74,12 @@ SIGNATURES = {
     "sigk_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_gram_ragged": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(Opts), _P,
                                         _P, _SZ, _P]),
+    "sigk_gram_ragged_workspace_size": (ctypes.c_int, [_P, _I64, _I64, _P, _I64,
+                                                       ctypes.POINTER(Opts), ctypes.POINTER(_SZ)]),
+    "sigk_backward_workspace_size": (ctypes.c_int, [_P, _I64, _I64, _P, _I64,
+                                                    ctypes.POINTER(Opts), ctypes.POINTER(_SZ)]),
+    "sigk_backward": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, ctypes.POINTER(Opts), _P,
+                                     _P, _SZ, _P]),
     "sigk_plan_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_run_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_backward_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),

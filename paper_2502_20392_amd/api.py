@@ -244,6 +244,58 @@ def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixe
     return _auto(run, order, order_hint)
 
 
+def gram_ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0,
+                fixed_depth=False):
+    """sigk_gram_ragged: k for each pair of a pool in one call (host offsets / pairs;
+    synchronous, not capturable; use RaggedPlan for repeated or captured runs)."""
+    pool = _check_paths(pool, "pool", 2)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    lib = _lib.load()
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    nb = ctypes.c_size_t()
+    _lib.check(lib.sigk_gram_ragged_workspace_size(off.ctypes.data_as(ctypes.c_void_p),
+                                                   off.shape[0] - 1, pool.shape[1],
+                                                   prs.ctypes.data_as(ctypes.c_void_p),
+                                                   prs.shape[0], ctypes.byref(o),
+                                                   ctypes.byref(nb)))
+    w = workspace(nb.value, pool.device)
+    out = torch.empty(prs.shape[0], dtype=torch.float64, device=pool.device)
+    _lib.check(lib.sigk_gram_ragged(_ptr(pool), off.ctypes.data_as(ctypes.c_void_p),
+                                    off.shape[0] - 1, pool.shape[1],
+                                    prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
+                                    ctypes.byref(o), _ptr(out), _ptr(w), w.numel(), _stream()))
+    _tls.ws = w
+    return out
+
+
+def backward(pool, offsets, pairs, grad_out, grad_pool=None, order=12, tol=None, tail_tol=None,
+             grid=0, fixed_depth=False):
+    """sigk_backward: grad_pool += d(sum_p grad_out[p] k_p)/d pool in one call (host
+    offsets / pairs; synchronous)."""
+    pool = _check_paths(pool, "pool", 2)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    grad_out = grad_out.contiguous().to(torch.float64)
+    if grad_pool is None:
+        grad_pool = torch.zeros_like(pool)
+    lib = _lib.load()
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    nb = ctypes.c_size_t()
+    _lib.check(lib.sigk_backward_workspace_size(off.ctypes.data_as(ctypes.c_void_p),
+                                                off.shape[0] - 1, pool.shape[1],
+                                                prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
+                                                ctypes.byref(o), ctypes.byref(nb)))
+    w = workspace(nb.value, pool.device)
+    _lib.check(lib.sigk_backward(_ptr(pool), off.ctypes.data_as(ctypes.c_void_p),
+                                 off.shape[0] - 1, pool.shape[1],
+                                 prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
+                                 _ptr(grad_out), ctypes.byref(o), _ptr(grad_pool), _ptr(w),
+                                 w.numel(), _stream()))
+    _tls.ws = w
+    return grad_pool
+
+
 # ------------------------------------------------------------------ autograd
 
 def _pool_and_pairs(X, Y, symmetric):

@@ -532,6 +532,18 @@ int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* 
     return SIGK_OK;
 }
 
+int sigk_gram_ragged_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
+                                    const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+                                    size_t* bytes) {
+    if (!bytes) return SIGK_EINVAL;
+    sigk_plan* pl = nullptr;
+    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
+    if (rc) return rc;
+    *bytes = pl->fwd_total;
+    sigk_plan_destroy(pl);
+    return SIGK_OK;
+}
+
 int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
                      const int32_t* pairs, int64_t npairs, const sigk_opts* o, double* out,
                      void* ws, size_t ws_bytes, void* stream) {
@@ -545,10 +557,38 @@ int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths,
     rc = sigk_plan_upload(pl, ws, ws_bytes, stream);
     if (!rc) rc = sigk_plan_run(pl, pool, out, ws, ws_bytes, stream);
     // the table copies come from pageable plan memory: wait before freeing it
-    if (!rc) {
-        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-        if (e != hipSuccess) rc = device_error(e);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (!rc && e != hipSuccess) rc = device_error(e);
+    sigk_plan_destroy(pl);
+    return rc;
+}
+
+int sigk_backward_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
+                                 const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+                                 size_t* bytes) {
+    if (!bytes) return SIGK_EINVAL;
+    sigk_plan* pl = nullptr;
+    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
+    if (rc) return rc;
+    *bytes = pl->bwd_total;
+    sigk_plan_destroy(pl);
+    return SIGK_OK;
+}
+
+int sigk_backward(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
+                  const int32_t* pairs, int64_t npairs, const double* grad_out, const sigk_opts* o,
+                  double* grad_pool, void* ws, size_t ws_bytes, void* stream) {
+    sigk_plan* pl = nullptr;
+    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
+    if (rc) return rc;
+    if (ws_bytes < pl->bwd_total) {
+        sigk_plan_destroy(pl);
+        return SIGK_EWORKSPACE;
     }
+    rc = sigk_plan_upload(pl, ws, ws_bytes, stream);
+    if (!rc) rc = sigk_plan_backward(pl, pool, grad_out, grad_pool, ws, ws_bytes, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (!rc && e != hipSuccess) rc = device_error(e);
     sigk_plan_destroy(pl);
     return rc;
 }

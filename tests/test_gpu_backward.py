@@ -244,3 +244,19 @@ def test_mmd_gradient_wrt_y_and_both(dev):
     assert abs(m.item() - mmd2_oracle(X, Y)) <= 1e-12
     assert np.abs(Xt.grad.cpu().numpy() - ref_x).max() <= 1e-10 * sc
     assert np.abs(Yt.grad.cpu().numpy() - ref_y).max() <= 1e-10 * sc
+
+
+def test_one_call_entry_points(dev):
+    """sigk_gram_ragged and sigk_backward (plan, upload, run in one call) against
+    the plan-based calls and the oracle."""
+    pool, off, _ = synth.ragged_paths(n_paths=5, lmin=20, lmax=120, d=4, smin=0.3, smax=0.6)
+    pairs = np.array([[0, 1], [2, 3], [4, 0], [3, 3]], dtype=np.int32)
+    w = synth.rng(4700).normal(size=len(pairs))
+    pd = T(pool, dev)
+    vals = sk().gram_ragged(pd, off, pairs, order=12).cpu().numpy()
+    ref = oracle.ragged(pool, off, pairs)
+    assert np.abs(vals - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    g = sk().backward(pd, off, pairs, T(w, dev), order=12).cpu().numpy()
+    plan = sk().RaggedPlan(off, pairs, 4, order=12, device=dev)
+    g2 = plan.backward(pd, T(w, dev)).cpu().numpy()
+    np.testing.assert_array_equal(g, g2)
