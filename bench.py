@@ -55,12 +55,20 @@ def parse():
     return ap.parse_args()
 
 
+# sources of the forward kernel's translation unit (host-side files excluded:
+# they do not change the kernel whose counters are stored)
+FWD_KERNEL_SOURCES = ("paper_2502_20392_amd/csrc/sigk_fwd.hip",
+                      "paper_2502_20392_amd/csrc/sigk_strip.h",
+                      "paper_2502_20392_amd/csrc/sigk_device.h",
+                      "paper_2502_20392_amd/csrc/sigk_internal.h",
+                      "paper_2502_20392_amd/build.py",
+                      "include/sigk.h")
+
+
 def kernel_source_digest():
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2502_20392_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in FWD_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 

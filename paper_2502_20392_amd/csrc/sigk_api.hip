@@ -307,6 +307,7 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     const int D = round_dim(d);
     if (!P || !D) return SIGK_EUNSUPPORTED;
     const GramLayout L = gram_layout(nx, ny, lx, ly, symmetric, P);
+    if (L.nprog > INT32_MAX) return SIGK_EINVAL;  // progress slots are indexed in 32 bits
     if (ws_bytes < L.total) return SIGK_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
