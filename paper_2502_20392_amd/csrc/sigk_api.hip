@@ -188,8 +188,8 @@ struct sigk_plan {
     int P = 0, D = 0;
     int64_t d = 0, npaths = 0, npairs = 0;
     std::vector<PairDesc> desc;
-    std::vector<Ticket> tickets;      // forward order (strip-major, largest first)
-    std::vector<Ticket> tickets_rev;  // adjoint order (top strip first)
+    std::vector<Ticket> tickets;      // forward order (longest remaining chain first)
+    std::vector<Ticket> tickets_rev;  // adjoint order (the same, top-down)
     int64_t nprog = 0;
     int64_t front_doubles = 0;        // forward frontier (one row per pair)
     int64_t snap_doubles = 0;         // adjoint: per-strip frontier snapshots
@@ -420,22 +420,44 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     pl->front_doubles = front;
     pl->snap_doubles = snap;
     pl->ckpt_doubles = ck;
-    // forward order: strip-major; within a strip level, pairs with more cells first
-    std::vector<int64_t> order((size_t)npairs);
-    for (int64_t p = 0; p < npairs; ++p) order[(size_t)p] = p;
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        const PairDesc &A = pl->desc[(size_t)a], &B = pl->desc[(size_t)b];
-        return (int64_t)(A.lx - 1) * (A.ly - 1) > (int64_t)(B.lx - 1) * (B.ly - 1);
-    });
-    for (int s = 0; s < max_strips; ++s)
-        for (int64_t p : order)
-            if (s < strips[(size_t)p]) pl->tickets.push_back({(int32_t)p, s});
-    // adjoint order: top strip of every pair first, then downwards
-    for (int s = 0; s < max_strips; ++s)
-        for (int64_t p : order) {
+    // Work order: longest remaining chain first.  The strips of a pair form a
+    // chain (each starts about one chunk plus the strip height behind its
+    // producer and sweeps all the pair's columns), so a ticket's remaining
+    // chain is its own sweep plus one such lag per strip still to follow it.
+    // Issuing long chains first keeps the deep strips of the largest pairs
+    // off the end of the launch.  Within a pair the producer always ranks
+    // first (its chain is one lag longer), so every wave waits on a wave that
+    // is already running.  Ties: more cells first, then pair index.
+    const int64_t lag = chunk_cols(P) + kWave - 1;
+    auto chain_order = [&](bool reverse) {
+        struct Key {
+            int64_t chain, cells;
+            int32_t p, s;
+        };
+        std::vector<Key> keys;
+        keys.reserve((size_t)prog);
+        for (int64_t p = 0; p < npairs; ++p) {
+            const PairDesc& q = pl->desc[(size_t)p];
             const int S = strips[(size_t)p];
-            if (s < S) pl->tickets_rev.push_back({(int32_t)p, S - 1 - s});
+            const int64_t m = std::max(q.lx - 1, 0), n = std::max(q.ly - 1, 0);
+            for (int s = 0; s < S; ++s) {
+                // forward: strips s+1.. follow; adjoint (top-down): strips ..s-1
+                const int64_t after = reverse ? s : S - 1 - s;
+                keys.push_back({after * lag + m + kWave - 1, m * n, (int32_t)p, s});
+            }
         }
+        std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+            if (a.chain != b.chain) return a.chain > b.chain;
+            if (a.cells != b.cells) return a.cells > b.cells;
+            return a.p < b.p;
+        });
+        std::vector<Ticket> t;
+        t.reserve(keys.size());
+        for (const Key& k : keys) t.push_back({k.p, k.s});
+        return t;
+    };
+    pl->tickets = chain_order(false);
+    pl->tickets_rev = chain_order(true);
     plan_layout(*pl);
     *plan = pl;
     return SIGK_OK;

@@ -100,7 +100,7 @@ struct FwdArgs {
 
 struct BwdArgs {
     FwdArgs f;               // geometry (table mode), depth thresholds
-    const Ticket* tickets;   // adjoint order (top strip of each pair first)
+    const Ticket* tickets;   // adjoint order (a pair's strips top-down, producers first)
     int64_t ntickets;
     const double* grad_out;  // [npairs] weights of the kernel values
     double* snap;            // frontier snapshots written by the checkpoint pass
