@@ -44,9 +44,55 @@ def _check_paths(t, name, ndim):
     return t.contiguous()
 
 
+def _check_buffer(t, name, numel, device, dtype=torch.float64, exact=False):
+    """A caller-supplied device buffer the kernels write: it must live on the
+    same GPU, have the right type, be contiguous (written in place) and hold
+    at least (exactly, if `exact`) `numel` elements."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device != device:
+        raise TypeError(f"{name} must be a CUDA tensor on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if (t.numel() != numel) if exact else (t.numel() < numel):
+        raise ValueError(f"{name} must have {'exactly' if exact else 'at least'} {numel} elements")
+    return t
+
+
+def _grad_out(g, npairs, device):
+    """Weights of the kernel values for a backward call: npairs values on the GPU."""
+    if not isinstance(g, torch.Tensor) or not g.is_cuda or g.device != device:
+        raise TypeError(f"grad_out must be a CUDA tensor on {device}")
+    g = g.reshape(-1).to(torch.float64).contiguous()
+    if g.numel() != npairs:
+        raise ValueError(f"grad_out must have {npairs} elements")
+    return g
+
+
+def _check_pool(pool, offsets, d):
+    """The pool must hold every point the offsets address, with d channels."""
+    pool = _check_paths(pool, "pool", 2)
+    if pool.shape[1] != d:
+        raise ValueError(f"pool has {pool.shape[1]} channels, the batch {d}")
+    need = int(offsets[-1]) if len(offsets) else 0
+    if pool.shape[0] < need:
+        raise ValueError(f"pool has {pool.shape[0]} points, the offsets address {need}")
+    return pool
+
+
 def workspace(nbytes, device):
     """A caller-owned device workspace (uint8 tensor) of at least nbytes."""
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _user_ws(ws, nbytes, device):
+    """The caller's workspace if it is large enough, else a new one."""
+    if ws is None:
+        return workspace(nbytes, device)
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.device != device \
+            or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise TypeError(f"ws must be a contiguous CUDA uint8 tensor on {device}")
+    return ws if ws.numel() >= nbytes else workspace(nbytes, device)
 
 
 def last_workspace():
@@ -93,7 +139,7 @@ def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_pair_workspace_size(x.shape[0], y.shape[0], x.shape[1],
                                                 ctypes.byref(o), ctypes.byref(nb)))
-        w = ws if ws is not None and ws.numel() >= nb.value else workspace(nb.value, x.device)
+        w = _user_ws(ws, nb.value, x.device)
         out = torch.empty((), dtype=torch.float64, device=x.device)
         _lib.check(lib.sigk_pair(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1],
                                  ctypes.byref(o), _ptr(out), _ptr(w), w.numel(), _stream()))
@@ -119,7 +165,7 @@ def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_gram_workspace_size(nx, ny, lx, ly, d, int(sym), ctypes.byref(o),
                                                 ctypes.byref(nb)))
-        w = ws if ws is not None and ws.numel() >= nb.value else workspace(nb.value, X.device)
+        w = _user_ws(ws, nb.value, X.device)
         G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
         _lib.check(lib.sigk_gram(_ptr(X), nx, _ptr(Y), ny, lx, ly, d, int(sym), ctypes.byref(o),
                                  _ptr(G), _ptr(w), w.numel(), _stream()))
@@ -166,6 +212,14 @@ class RaggedPlan:
             except Exception:
                 pass
 
+    def _pool(self, pool):
+        pool = _check_pool(pool, self.offsets, self.d)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        if pool.device != self.device:
+            raise ValueError(f"pool is on {pool.device}, the plan on {self.device}")
+        return pool
+
     def ensure_workspace(self, backward=False):
         need = self.bwd_ws_bytes if backward else self.ws_bytes
         if self.ws is None or self.ws.numel() < need:
@@ -182,10 +236,11 @@ class RaggedPlan:
     def run(self, pool, out=None):
         """out[p] = k(pairs[p]) for pool [sum len, d]; no host-device copies (capturable
         once the workspace exists)."""
-        pool = _check_paths(pool, "pool", 2)
+        pool = self._pool(pool)
         ws = self.ensure_workspace()
         if out is None:
             out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
+        _check_buffer(out, "out", self.npairs, pool.device)
         _lib.check(_lib.load().sigk_plan_run(self._h, _ptr(pool), _ptr(out), _ptr(ws),
                                              ws.numel(), _stream()))
         _tls.ws = ws
@@ -206,10 +261,11 @@ class RaggedPlan:
     def run_checkpointed(self, pool, out=None):
         """As ``run``, by the checkpointing forward sweep: the checkpoints stay in
         the plan's workspace for ``backward(..., checkpointed=True)``."""
-        pool = _check_paths(pool, "pool", 2)
+        pool = self._pool(pool)
         ws = self.ensure_workspace(backward=True)
         if out is None:
             out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
+        _check_buffer(out, "out", self.npairs, pool.device)
         _lib.check(_lib.load().sigk_plan_run_checkpointed(self._h, _ptr(pool), _ptr(out),
                                                           _ptr(ws), ws.numel(), _stream()))
         _tls.ws = ws
@@ -218,11 +274,12 @@ class RaggedPlan:
     def backward(self, pool, grad_out, grad_pool=None, checkpointed=False):
         """grad_pool += d(sum_p grad_out[p] k_p)/d pool.  checkpointed: reuse the
         checkpoints of the last ``run_checkpointed`` on the same pool."""
-        pool = _check_paths(pool, "pool", 2)
-        grad_out = grad_out.contiguous().to(torch.float64)
+        pool = self._pool(pool)
+        grad_out = _grad_out(grad_out, self.npairs, pool.device)
         ws = self.ensure_workspace(backward=True)
         if grad_pool is None:
             grad_pool = torch.zeros_like(pool)
+        _check_buffer(grad_pool, "grad_pool", pool.numel(), pool.device, exact=True)
         fn = (_lib.load().sigk_plan_backward_checkpointed if checkpointed
               else _lib.load().sigk_plan_backward)
         _lib.check(fn(self._h, _ptr(pool), _ptr(grad_out), _ptr(grad_pool), _ptr(ws), ws.numel(),
@@ -234,7 +291,7 @@ class RaggedPlan:
 def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False,
            order_hint=6):
     """k for each pair of paths of a concatenated pool (host offsets / pairs)."""
-    pool = _check_paths(pool, "pool", 2)
+    pool = _check_pool(pool, np.asarray(offsets), _check_paths(pool, "pool", 2).shape[1])
 
     def run(p):
         plan = RaggedPlan(offsets, pairs, pool.shape[1], p, tol, tail_tol, grid, fixed_depth,
@@ -248,8 +305,8 @@ def gram_ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0,
                 fixed_depth=False):
     """sigk_gram_ragged: k for each pair of a pool in one call (host offsets / pairs;
     synchronous, not capturable; use RaggedPlan for repeated or captured runs)."""
-    pool = _check_paths(pool, "pool", 2)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
+    pool = _check_pool(pool, off, _check_paths(pool, "pool", 2).shape[1])
     prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
     lib = _lib.load()
     o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
@@ -273,12 +330,13 @@ def backward(pool, offsets, pairs, grad_out, grad_pool=None, order=12, tol=None,
              grid=0, fixed_depth=False):
     """sigk_backward: grad_pool += d(sum_p grad_out[p] k_p)/d pool in one call (host
     offsets / pairs; synchronous)."""
-    pool = _check_paths(pool, "pool", 2)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
+    pool = _check_pool(pool, off, _check_paths(pool, "pool", 2).shape[1])
     prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
-    grad_out = grad_out.contiguous().to(torch.float64)
+    grad_out = _grad_out(grad_out, prs.shape[0], pool.device)
     if grad_pool is None:
         grad_pool = torch.zeros_like(pool)
+    _check_buffer(grad_pool, "grad_pool", pool.numel(), pool.device, exact=True)
     lib = _lib.load()
     o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
     nb = ctypes.c_size_t()
