@@ -9,6 +9,8 @@ depth, wavefront propagation over the 999,999 x 999,999 grid, corner value.
 Also measured (field "workloads"): the 64 x 64 Gram (length 1024, d 16,
 sigma 1 and 4), the ragged batch of 512 pairs (graph replay, autotuned order),
 MMD^2 forward + backward (32 + 32 paths, length 2048, d 8) and the 8 x 8 Gram.
+Every workload runs at the smallest compiled edge order whose run raises no
+truncation warning (the library's tail check), chosen before timing.
 
 Prints ONE JSON line.  "roofline" covers the forward kernel of the headline
 workload: algorithmic FP64 flops per launch (counted on the device: the
@@ -30,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 FIRST_ORDER = 4  # order search for the headline pair starts here
+MMD_FIRST_ORDER = 8  # and for the MMD^2 workload
 METRIC = "Goursat grid cells/s (fwd, fwd+bwd) at rel err ≤1e-10 vs FP64 oracle"
 
 
@@ -113,21 +116,28 @@ def extras(torch, sk, dev, only=""):
     def frac(flops, ms):
         return flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS
 
-    for name, sig, order in (("gram64_len1024_d16_sigma1", 1.0, 12),
-                             ("gram64_len1024_d16_sigma4", 4.0, 20)):
-        if not want(name):
-            continue
-        X = torch.from_numpy(synth.gram_mid(sig)).to(dev)
+    def gram_entry(name, X, first):
+        # the smallest compiled order from `first` up with no truncation
+        # warning (the library's tail check), chosen before timing
+        from paper_2502_20392_amd import _lib
+        tried = []
+        for order in [p for p in _lib.ORDERS if p >= first]:
+            sk.gram(X, order=order)
+            st = sk.counters()["status"]
+            tried.append({"order": order, "status": st})
+            if not st & _lib.WARN_TRUNC:
+                break
         ms = timed(lambda: sk.gram(X, order=order), torch)
         c = sk.counters()
         res[name] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": order,
-                     "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+                     "orders_tried": tried, "fp64_frac": frac(c["flops"], ms),
+                     "status": c["status"]}
+
+    for name, sig in (("gram64_len1024_d16_sigma1", 1.0), ("gram64_len1024_d16_sigma4", 4.0)):
+        if want(name):
+            gram_entry(name, torch.from_numpy(synth.gram_mid(sig)).to(dev), 8)
     if want("gram8_len128_d3"):
-        X = torch.from_numpy(synth.gram_small()).to(dev)
-        ms = timed(lambda: sk.gram(X, order=12), torch)
-        c = sk.counters()
-        res["gram8_len128_d3"] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": 12,
-                                  "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+        gram_entry("gram8_len128_d3", torch.from_numpy(synth.gram_small()).to(dev), 4)
     if want("ragged512_len64to4096_d32_graph"):
         ragged(torch, sk, dev, synth, tune, frac, res)
     if want("mmd_32x32_len2048_d8_fwd_bwd"):
@@ -153,13 +163,25 @@ def ragged(torch, sk, dev, synth, tune, frac, res):
 
 def mmd(torch, sk, dev, synth, res):
     # MMD^2 forward + backward (gradient with respect to X)
+    from paper_2502_20392_amd import _lib
     Xm, Ym = synth.mmd_sets()
     Xt = torch.from_numpy(Xm).to(dev).requires_grad_(True)
     Yt = torch.from_numpy(Ym).to(dev)
+    # edge order: the smallest compiled order from MMD_FIRST_ORDER up whose
+    # forward blocks (XX, YY, XY) raise no truncation warning (untimed)
+    tried = []
+    for order in [p for p in _lib.ORDERS if p >= MMD_FIRST_ORDER]:
+        st = 0
+        for A, B in ((Xt.detach(), None), (Yt, None), (Xt.detach(), Yt)):
+            sk.gram(A, B, order=order)
+            st |= sk.counters()["status"]
+        tried.append({"order": order, "status": st})
+        if not st & _lib.WARN_TRUNC:
+            break
 
     def fb():
         Xt.grad = None
-        sk.mmd2(Xt, Yt, order=10).backward()
+        sk.mmd2(Xt, Yt, order=order).backward()
 
     ms = timed(fb, torch, steps=2)
     nx, lx = Xm.shape[0], Xm.shape[1]
@@ -168,7 +190,8 @@ def mmd(torch, sk, dev, synth, res):
                  + nx * ny * (lx - 1) * (ly - 1))
     bwd_cells = nx * (nx + 1) // 2 * (lx - 1) ** 2 + nx * ny * (lx - 1) * (ly - 1)
     res["mmd_32x32_len2048_d8_fwd_bwd"] = {
-        "cells_per_s": fwd_cells / (ms / 1e3), "ms": ms, "order": 10,
+        "cells_per_s": fwd_cells / (ms / 1e3), "ms": ms, "order": order,
+        "orders_tried": tried, "status": st,
         "fwd_cells": fwd_cells, "bwd_cells": bwd_cells,
         "note": "fwd+bwd: forward cells over the time of forward plus backward"}
 
