@@ -406,7 +406,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
         front += m * P;
         // adjoint: frontier snapshot per strip and wave-state checkpoints
         q.ckpt_off = ck;
-        ck += (int64_t)S * ckpt_strip_doubles(m, P);
+        ck += (int64_t)S * ckpt_strip_doubles(m, P, D);
         q.snap_off = snap;
         snap += (int64_t)S * m * P;
         pl->cells += (uint64_t)(m * n);
@@ -428,7 +428,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     // off the end of the launch.  Within a pair the producer always ranks
     // first (its chain is one lag longer), so every wave waits on a wave that
     // is already running.  Ties: more cells first, then pair index.
-    const int64_t lag = chunk_cols(P) + kWave - 1;
+    const int64_t lag = chunk_cols(P, D) + kWave - 1;
     auto chain_order = [&](bool reverse) {
         struct Key {
             int64_t chain, cells;

@@ -8,7 +8,8 @@
 // top-edge series it produces moves to lane j+1 for the next step by a DPP
 // wave shift.  Lane 0 takes its bottom edge from the frontier row written by
 // the strip below; lane 63 writes its top edge to the frontier for the strip
-// above.  Frontier columns are exchanged between strips in chunks of 32:
+// above.  Frontier columns are exchanged between strips in chunks (64
+// columns for orders up to 5 at 8 channels, else 32):
 // lane 63's edges are staged in LDS and written out with device-coherent
 // stores, followed by a progress flag per strip; the strip above polls the
 // flag and reads the chunk with device-coherent loads (no cache maintenance).
@@ -25,7 +26,7 @@
 // Neumann depth.  Term n (the entries of C with min(i, j) = n, the n-th term
 // of the series of Prop. 2.5) is bounded by |c|^n/(n!)^2 relative to the edge
 // data.  It is applied while |c| may exceed tau_n = (tol (n!)^2)^(1/n)
-// anywhere in the cells a chunk of 32 steps covers, using the exact bound
+// anywhere in the cells a chunk of steps covers, using the exact bound
 // |c| = |<dx_k, dy_l>| <= |dx_k| |dy_l| (Cauchy-Schwarz).  The depth is
 // therefore uniform over the wave and known before each chunk, so the step
 // loop carries no data-dependent branch.
@@ -46,9 +47,11 @@ __device__ __forceinline__ int ring_slot(int col) {
 
 template <int P, int D>
 struct LdsStrip {
+    static_assert(ring_cols(P) >= chunk_cols(P, D) + kWave - 1,
+                  "the ring must hold the columns a chunk's steps touch");
     double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
-    double bin[chunk_cols(P) * P];  // bottom edges of the current chunk (lane 0)
-    double tout[chunk_cols(P) * P]; // top edges of the top lane, current chunk
+    double bin[chunk_cols(P, D) * P];  // bottom edges of the current chunk (lane 0)
+    double tout[chunk_cols(P, D) * P]; // top edges of the top lane, current chunk
     float nrm2[ring_cols(P)];       // |dx_k|^2 of the same columns, rounded up
 };
 
@@ -274,7 +277,7 @@ struct StripCtx {
     // the Neumann depth for steps [c0, c0+CH).
     __device__ bool load_chunk(int c0) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P);
+        const int CH = chunk_cols(P, D);
         const int nc = min(CH, g.m - c0);
         // Issue every load before the first wait: the path points of the
         // chunk's columns (lane j: column c0 + j, clamped to the chunk), then
@@ -290,7 +293,7 @@ struct StripCtx {
         }
         if (has_below) {
             if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
-            constexpr int NB = (chunk_cols(P) * P + kWave - 1) / kWave;
+            constexpr int NB = (chunk_cols(P, D) * P + kWave - 1) / kWave;
             const CoherentSpan src(Fin + (int64_t)c0 * P, nc * P);
             double bv[NB];
 #pragma unroll
@@ -330,7 +333,7 @@ struct StripCtx {
     // The top lane has produced columns [c0, c1) (staged in LDS): write them
     // to the frontier with coalesced device-coherent stores and publish.
     __device__ void flush(int c0, int c1) {
-        const int CH = chunk_cols(P);
+        const int CH = chunk_cols(P, D);
         double* dst = Fout + (int64_t)c0 * P;
         const int base = (c0 % CH) * P;
         for (int e = lane_id(); e < (c1 - c0) * P; e += kWave) store_coherent(&dst[e], L.tout[base + e]);
@@ -371,7 +374,7 @@ struct StripCtx {
     template <bool EDGE, int QC>
     __device__ __forceinline__ void step(int t, bool act) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P);
+        const int CH = chunk_cols(P, D);
         const int col = t - lane;
         double A[P];
         const double* bsrc = &L.bin[((unsigned)t % (unsigned)CH) * P];  // t >= 0
@@ -414,7 +417,7 @@ struct StripCtx {
                 Ac[i] = An[i];
             }
             if (has_above && lane == kWave - 1 && act) {
-                double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P)) * P];
+                double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P, D)) * P];
                 lds_copy<P>(dst, An);
             }
             return;
@@ -443,7 +446,7 @@ struct StripCtx {
             Ac[i] = An[i];
         }
         if (has_above && lane == kWave - 1 && act) {
-            double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P)) * P];
+            double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P, D)) * P];
 #pragma unroll
             for (int i = 0; i < P; ++i) dst[i] = An[i];
         }
@@ -469,7 +472,7 @@ struct StripCtx {
     template <bool EDGE>
     __device__ bool run(int t0, int t1) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P);
+        const int CH = chunk_cols(P, D);
         const int m = g.m;
         int t = t0;
         while (t < t1) {
@@ -547,7 +550,7 @@ struct StripCtx {
         }
         if (!has_below) {
             // bottom row of the grid: K = 1 on the axis t = 0
-            const int CH = chunk_cols(P);
+            const int CH = chunk_cols(P, D);
             for (int e = lane; e < CH * P; e += kWave) L.bin[e] = (e % P) == 0 ? 1.0 : 0.0;
             __syncthreads();
         }
