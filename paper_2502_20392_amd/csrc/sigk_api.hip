@@ -406,7 +406,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
         front += m * P;
         // adjoint: frontier snapshot per strip and wave-state checkpoints
         q.ckpt_off = ck;
-        ck += (int64_t)S * ckpt_strip_doubles(m, P, D);
+        ck += (int64_t)S * ckpt_strip_doubles(m, P);
         q.snap_off = snap;
         snap += (int64_t)S * m * P;
         pl->cells += (uint64_t)(m * n);
@@ -428,7 +428,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     // off the end of the launch.  Within a pair the producer always ranks
     // first (its chain is one lag longer), so every wave waits on a wave that
     // is already running.  Ties: more cells first, then pair index.
-    const int64_t lag = chunk_cols(P, D) + kWave - 1;
+    const int64_t lag_fwd = fwd_chunk_cols(P, D) + kWave - 1, lag_adj = chunk_cols(P) + kWave - 1;
     auto chain_order = [&](bool reverse) {
         struct Key {
             int64_t chain, cells;
@@ -443,7 +443,8 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
             for (int s = 0; s < S; ++s) {
                 // forward: strips s+1.. follow; adjoint (top-down): strips ..s-1
                 const int64_t after = reverse ? s : S - 1 - s;
-                keys.push_back({after * lag + m + kWave - 1, m * n, (int32_t)p, s});
+                keys.push_back({after * (reverse ? lag_adj : lag_fwd) + m + kWave - 1, m * n,
+                                (int32_t)p, s});
             }
         }
         std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {

@@ -29,7 +29,8 @@ namespace sigk {
 
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
-    __shared__ LdsStrip<P, D> L;
+    constexpr int CH = chunk_cols(P);
+    __shared__ LdsStrip<P, D, CH> L;
     Acc acc;
     const int lane = lane_id();
     for (;;) {
@@ -41,12 +42,12 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
         const int pair = a.tickets[t].pair, strip = a.tickets[t].strip;
         Geo g = resolve(a, pair, P, 0);
         const PairDesc& pd = a.desc[pair];
-        StripCtx<P, D> S(a, g, L, acc, strip);
+        StripCtx<P, D, CH> S(a, g, L, acc, strip);
         const int64_t row = (int64_t)g.m * P;
         S.Fin = snap + pd.snap_off + (int64_t)strip * row;
         S.Fout = snap + pd.snap_off + (int64_t)(strip + 1) * row;
         S.prog = a.progress + g.prog;
-        double* ck = a.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P, D);
+        double* ck = a.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
         S.ck = ck;
         S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
         S.ck_every = kCkptEvery;
@@ -61,13 +62,13 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
 
 template <int P, int D>
 struct LdsBwd {
-    static_assert(ring_cols(P) >= chunk_cols(P, D) + kWave - 1,
+    static_assert(ring_cols(P) >= chunk_cols(P) + kWave - 1,
                   "the rings must hold a chunk and the 63 columns before it");
     double dx[D * ring_cols(P)];      // increments of x by ring slot
     double gx[D * ring_cols(P)];      // dL/d(dx) being accumulated, by ring slot
-    double bin[chunk_cols(P, D) * P];    // primal bottom edges (lane 0) of a chunk
-    double lin[2 * chunk_cols(P, D) * P];  // top-edge cotangents (top lane), 2 chunks
-    double lout[chunk_cols(P, D) * P];   // bottom-edge cotangents (lane 0), 1 chunk
+    double bin[chunk_cols(P) * P];    // primal bottom edges (lane 0) of a chunk
+    double lin[2 * chunk_cols(P) * P];  // top-edge cotangents (top lane), 2 chunks
+    double lout[chunk_cols(P) * P];   // bottom-edge cotangents (lane 0), 1 chunk
 };
 
 template <int P, int D>
@@ -115,14 +116,14 @@ struct StripBwd {
     }
 
     __device__ bool load_lin_down_to(int lo_needed) {
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int lane = lane_id();
         while (lin_lo > lo_needed && lin_lo > 0) {
             const int c0 = lin_lo - CH;
             const int nc = min(CH, m - c0);
             if (!wait_flag(&lam_prog[s + 1], m - c0, a.hdr, a.watchdog_ticks)) return false;
             double* dst = &L.lin[((c0 / CH) & 1) * CH * P];
-            constexpr int NB = (chunk_cols(P, D) * P + kWave - 1) / kWave;
+            constexpr int NB = (chunk_cols(P) * P + kWave - 1) / kWave;
             const CoherentSpan src(lam_row + (int64_t)c0 * P, nc * P);
             double v[NB];
 #pragma unroll
@@ -137,7 +138,7 @@ struct StripBwd {
     }
 
     __device__ void load_bin(int chunk) {
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int lane = lane_id();
         const int c0 = chunk * CH;
         const int nc = min(CH, m - c0);
@@ -154,7 +155,7 @@ struct StripBwd {
     // columns [c0, c1) are final: publish the bottom-edge cotangents to the
     // strip below and add dL/d(dx) to the path's gradient scratch
     __device__ void flush_cols(int c0, int c1) {
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int lane = lane_id();
         __syncthreads();
         const int nc = c1 - c0;
@@ -178,7 +179,7 @@ struct StripBwd {
     }
 
     __device__ __forceinline__ int depth_at(int t) const {
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int k = min(t, m - 1) / CH;
         return uniform((int)ckq[k]);
     }
@@ -205,7 +206,7 @@ struct StripBwd {
     template <int Q>
     __device__ void segment(int q, int t0, int t1) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int W = kCkptEvery;
         double B[P], Ac[P];
         {
@@ -320,7 +321,7 @@ struct StripBwd {
 
     __device__ bool sweep() {
         const int lane = lane_id();
-        const int CH = chunk_cols(P, D);
+        const int CH = chunk_cols(P);
         const int W = kCkptEvery;
         m = g.m;
         const int row0 = s * kWave;
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
         StripBwd<P, D> S(b, g, L, strip);
         S.pd = &pd;
         S.scratch = scratch;
-        S.ck = b.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P, D);
+        S.ck = b.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
         S.ckq = S.ck + ckpt_states(g.m) * 2 * P * kWave;
         S.snap_in = b.snap + pd.snap_off + (int64_t)strip * g.m * P;
         S.lam_row = b.lam_front + pd.front_off;

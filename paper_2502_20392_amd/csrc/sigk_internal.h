@@ -22,13 +22,18 @@ constexpr int kMaxP = 24;   // largest compiled edge order
     X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) X(20, 16) X(24, 16) \
     X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32) X(20, 32) X(24, 32)
 
-// Frontier chunk (columns per progress flag) for edge order P, channel
+// Frontier chunk (columns per progress flag) of the checkpointing forward
+// sweep and of the adjoint, for edge order P.
+__host__ __device__ constexpr int chunk_cols(int P) { return 32; }
+// Frontier chunk of the plain forward sweep, for edge order P and channel
 // bucket D.  Wider chunks halve the flag waits and frontier loads per column
 // but lengthen the start lag between strips and take LDS (a wave less per
 // CU at D = 8); 64 columns (the most a 128-column ring allows: it holds
 // [c0-63, c0+chunk)) pay off where a step is shortest: orders 4 and 5 at
-// D = 8 ran 5-6% faster on the long pair, order 6 ran 6% slower.
-__host__ __device__ constexpr int chunk_cols(int P, int D) { return P <= 5 && D <= 8 ? 64 : 32; }
+// D = 8 ran 5-6% faster on the long pair, order 6 ran 6% slower.  (The
+// adjoint path keeps 32: there the wider buffers cost more waves than the
+// exchange saves.)
+__host__ __device__ constexpr int fwd_chunk_cols(int P, int D) { return P <= 5 && D <= 8 ? 64 : 32; }
 // Columns of the increment ring in LDS: it holds [c0-63, c0+chunk) while the
 // steps of chunk c0 run.
 __host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }
@@ -55,9 +60,9 @@ constexpr int kCkptEvery = 16;
 __host__ __device__ constexpr int64_t ckpt_states(int64_t m) {
     return (m + kWave + kCkptEvery - 1) / kCkptEvery + 1;
 }
-__host__ __device__ constexpr int64_t ckpt_strip_doubles(int64_t m, int P, int D) {
+__host__ __device__ constexpr int64_t ckpt_strip_doubles(int64_t m, int P) {
     return ckpt_states(m) * 2 * P * kWave +
-           ((m + chunk_cols(P, D) - 1) / chunk_cols(P, D) + kWave - 1) / kWave * kWave;
+           ((m + chunk_cols(P) - 1) / chunk_cols(P) + kWave - 1) / kWave * kWave;
 }
 
 struct Ticket {

@@ -45,13 +45,13 @@ __device__ __forceinline__ int ring_slot(int col) {
         return (int)((unsigned)(col + RB) % (unsigned)RB);
 }
 
-template <int P, int D>
+template <int P, int D, int CH>
 struct LdsStrip {
-    static_assert(ring_cols(P) >= chunk_cols(P, D) + kWave - 1,
+    static_assert(ring_cols(P) >= CH + kWave - 1,
                   "the ring must hold the columns a chunk's steps touch");
     double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
-    double bin[chunk_cols(P, D) * P];  // bottom edges of the current chunk (lane 0)
-    double tout[chunk_cols(P, D) * P]; // top edges of the top lane, current chunk
+    double bin[CH * P];   // bottom edges of the current chunk (lane 0)
+    double tout[CH * P];  // top edges of the top lane, current chunk
     float nrm2[ring_cols(P)];       // |dx_k|^2 of the same columns, rounded up
 };
 
@@ -244,11 +244,12 @@ __device__ __forceinline__ void lds_copy(double* dst, const double* src) {
     }
 }
 
-template <int P, int D>
+// CH: columns per frontier chunk.
+template <int P, int D, int CH>
 struct StripCtx {
     const FwdArgs& a;
     Geo& g;
-    LdsStrip<P, D>& L;
+    LdsStrip<P, D, CH>& L;
     Acc& acc;
     int s;              // strip index
     int nrows;          // valid rows in this strip (<= 64)
@@ -270,14 +271,13 @@ struct StripCtx {
     double* ckq;        // Neumann depth per chunk (with ck)
     int ck_every;
 
-    __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D>& L_, Acc& acc_, int s_)
+    __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
 
     // Load columns [c0, c0+CH) (increments, their norms, bottom edges) and set
     // the Neumann depth for steps [c0, c0+CH).
     __device__ bool load_chunk(int c0) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P, D);
         const int nc = min(CH, g.m - c0);
         // Issue every load before the first wait: the path points of the
         // chunk's columns (lane j: column c0 + j, clamped to the chunk), then
@@ -293,7 +293,7 @@ struct StripCtx {
         }
         if (has_below) {
             if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
-            constexpr int NB = (chunk_cols(P, D) * P + kWave - 1) / kWave;
+            constexpr int NB = (CH * P + kWave - 1) / kWave;
             const CoherentSpan src(Fin + (int64_t)c0 * P, nc * P);
             double bv[NB];
 #pragma unroll
@@ -333,7 +333,6 @@ struct StripCtx {
     // The top lane has produced columns [c0, c1) (staged in LDS): write them
     // to the frontier with coalesced device-coherent stores and publish.
     __device__ void flush(int c0, int c1) {
-        const int CH = chunk_cols(P, D);
         double* dst = Fout + (int64_t)c0 * P;
         const int base = (c0 % CH) * P;
         for (int e = lane_id(); e < (c1 - c0) * P; e += kWave) store_coherent(&dst[e], L.tout[base + e]);
@@ -374,7 +373,6 @@ struct StripCtx {
     template <bool EDGE, int QC>
     __device__ __forceinline__ void step(int t, bool act) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P, D);
         const int col = t - lane;
         double A[P];
         const double* bsrc = &L.bin[((unsigned)t % (unsigned)CH) * P];  // t >= 0
@@ -417,7 +415,7 @@ struct StripCtx {
                 Ac[i] = An[i];
             }
             if (has_above && lane == kWave - 1 && act) {
-                double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P, D)) * P];
+                double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
                 lds_copy<P>(dst, An);
             }
             return;
@@ -446,7 +444,7 @@ struct StripCtx {
             Ac[i] = An[i];
         }
         if (has_above && lane == kWave - 1 && act) {
-            double* dst = &L.tout[((unsigned)col % (unsigned)chunk_cols(P, D)) * P];
+            double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
 #pragma unroll
             for (int i = 0; i < P; ++i) dst[i] = An[i];
         }
@@ -472,7 +470,6 @@ struct StripCtx {
     template <bool EDGE>
     __device__ bool run(int t0, int t1) {
         const int lane = lane_id();
-        const int CH = chunk_cols(P, D);
         const int m = g.m;
         int t = t0;
         while (t < t1) {
@@ -550,8 +547,7 @@ struct StripCtx {
         }
         if (!has_below) {
             // bottom row of the grid: K = 1 on the axis t = 0
-            const int CH = chunk_cols(P, D);
-            for (int e = lane; e < CH * P; e += kWave) L.bin[e] = (e % P) == 0 ? 1.0 : 0.0;
+                for (int e = lane; e < CH * P; e += kWave) L.bin[e] = (e % P) == 0 ? 1.0 : 0.0;
             __syncthreads();
         }
         const int T = m + nrows - 1;
