@@ -29,8 +29,8 @@ namespace sigk {
 
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
-    constexpr int CH = chunk_cols(P);
-    __shared__ LdsStrip<P, D, CH> L;
+    constexpr int CH = chunk_cols(P), RB = ring_cols(P);
+    __shared__ LdsStrip<P, D, CH, RB> L;
     Acc acc;
     const int lane = lane_id();
     for (;;) {
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
         const int pair = a.tickets[t].pair, strip = a.tickets[t].strip;
         Geo g = resolve(a, pair, P, 0);
         const PairDesc& pd = a.desc[pair];
-        StripCtx<P, D, CH> S(a, g, L, acc, strip);
+        StripCtx<P, D, CH, RB> S(a, g, L, acc, strip);
         const int64_t row = (int64_t)g.m * P;
         S.Fin = snap + pd.snap_off + (int64_t)strip * row;
         S.Fout = snap + pd.snap_off + (int64_t)(strip + 1) * row;

@@ -21,8 +21,8 @@ namespace sigk {
 
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 6 && D <= 8 ? 3 : 1))) fwd_kernel(FwdArgs a) {
-    constexpr int CH = fwd_chunk_cols(P, D);
-    __shared__ LdsStrip<P, D, CH> L;
+    constexpr int CH = fwd_chunk_cols(P, D), RB = fwd_ring_cols(P, D);
+    __shared__ LdsStrip<P, D, CH, RB> L;
     Acc acc;
     const int lane = lane_id();
     for (;;) {
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <=
             strip = a.tickets[t].strip;
         }
         Geo g = resolve(a, pair, P, 0);
-        StripCtx<P, D, CH> S(a, g, L, acc, strip);
+        StripCtx<P, D, CH, RB> S(a, g, L, acc, strip);
         S.Fout = a.frontier + g.front;
         S.Fin = S.Fout;
         S.prog = a.progress + g.prog;

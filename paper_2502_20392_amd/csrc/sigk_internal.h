@@ -29,14 +29,22 @@ __host__ __device__ constexpr int chunk_cols(int P) { return 32; }
 // bucket D.  Wider chunks halve the flag waits and frontier loads per column
 // but lengthen the start lag between strips and take LDS (a wave less per
 // CU at D = 8); 64 columns (the most a 128-column ring allows: it holds
-// [c0-63, c0+chunk)) pay off where a step is shortest: orders 4 and 5 at
-// D = 8 ran 5-6% faster on the long pair, order 6 ran 6% slower.  (The
-// adjoint path keeps 32: there the wider buffers cost more waves than the
-// exchange saves.)
-__host__ __device__ constexpr int fwd_chunk_cols(int P, int D) { return P <= 5 && D <= 8 ? 64 : 32; }
+// [c0-63, c0+chunk)) pay off at orders 4 and 5 with D = 8 (5-6% faster on
+// the long pair, order 6 ran 6% slower: a wave less per CU) and at orders
+// 10-20 with D <= 16, which run one wave per SIMD anyway (Gram workloads
+// 6-9% faster).  (The adjoint path keeps 32: there the wider buffers cost
+// more waves than the exchange saves.)
+__host__ __device__ constexpr int fwd_chunk_cols(int P, int D) {
+    return (P <= 5 && D <= 8) || (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
+}
 // Columns of the increment ring in LDS: it holds [c0-63, c0+chunk) while the
-// steps of chunk c0 run.
+// steps of chunk c0 run.  ring_cols: the checkpointing sweep and the adjoint;
+// fwd_ring_cols: the plain forward sweep, 128 wherever its chunks are 64
+// columns wide.
 __host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }
+__host__ __device__ constexpr int fwd_ring_cols(int P, int D) {
+    return fwd_chunk_cols(P, D) == 64 ? 128 : ring_cols(P);
+}
 
 // Per-pair geometry for table mode (ragged batches).  Offsets in elements.
 struct PairDesc {

@@ -35,24 +35,29 @@
 
 namespace sigk {
 
-// Ring slot of column col (col >= -ring_cols(P)).
-template <int P>
-__device__ __forceinline__ int ring_slot(int col) {
-    constexpr int RB = ring_cols(P);
+// Slot of column col in a ring of RB columns (col >= -RB).
+template <int RB>
+__device__ __forceinline__ int ring_slot_of(int col) {
     if constexpr ((RB & (RB - 1)) == 0)
         return col & (RB - 1);
     else
         return (int)((unsigned)(col + RB) % (unsigned)RB);
 }
 
-template <int P, int D, int CH>
+// The same for the adjoint's rings (ring_cols(P) columns).
+template <int P>
+__device__ __forceinline__ int ring_slot(int col) {
+    return ring_slot_of<ring_cols(P)>(col);
+}
+
+template <int P, int D, int CH, int RB>
 struct LdsStrip {
-    static_assert(ring_cols(P) >= CH + kWave - 1,
+    static_assert(RB >= CH + kWave - 1,
                   "the ring must hold the columns a chunk's steps touch");
-    double dx[D * ring_cols(P)];    // increments of x, [channel][ring slot]
+    double dx[D * RB];              // increments of x, [channel][ring slot]
     double bin[CH * P];   // bottom edges of the current chunk (lane 0)
     double tout[CH * P];  // top edges of the top lane, current chunk
-    float nrm2[ring_cols(P)];       // |dx_k|^2 of the same columns, rounded up
+    float nrm2[RB];                 // |dx_k|^2 of the same columns, rounded up
 };
 
 struct Acc {
@@ -244,12 +249,12 @@ __device__ __forceinline__ void lds_copy(double* dst, const double* src) {
     }
 }
 
-// CH: columns per frontier chunk.
-template <int P, int D, int CH>
+// CH: columns per frontier chunk; RB: columns of the increment ring.
+template <int P, int D, int CH, int RB>
 struct StripCtx {
     const FwdArgs& a;
     Geo& g;
-    LdsStrip<P, D, CH>& L;
+    LdsStrip<P, D, CH, RB>& L;
     Acc& acc;
     int s;              // strip index
     int nrows;          // valid rows in this strip (<= 64)
@@ -271,7 +276,7 @@ struct StripCtx {
     double* ckq;        // Neumann depth per chunk (with ck)
     int ck_every;
 
-    __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH>& L_, Acc& acc_, int s_)
+    __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH, RB>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
 
     // Load columns [c0, c0+CH) (increments, their norms, bottom edges) and set
@@ -307,20 +312,20 @@ struct StripCtx {
 #pragma unroll
             for (int ch = 0; ch < D; ++ch) {
                 const double v = ch < a.d ? hi[ch] - lo[ch] : 0.0;
-                L.dx[ch * ring_cols(P) + ring_slot<P>(col)] = v;
+                L.dx[ch * RB + ring_slot_of<RB>(col)] = v;
                 n2 = fma(v, v, n2);
             }
             // stored as a float no smaller than n2 (relative slack above the
             // float rounding, floor at the smallest normal float)
-            L.nrm2[ring_slot<P>(col)] =
+            L.nrm2[ring_slot_of<RB>(col)] =
                 (float)fmax(n2 * (1.0 + 1e-6), n2 > 0.0 ? 1.2e-38 : 0.0);
         }
         __syncthreads();
         // columns touched by steps [c0, c0+CH): [c0-63, c0+nc)
         double w = 0.0;
         const int k1 = c0 - (kWave - 1) + lane, k2 = c0 + lane;
-        if (k1 >= 0 && k1 < c0 + nc) w = (double)L.nrm2[ring_slot<P>(k1)];
-        if (lane < nc) w = fmax(w, (double)L.nrm2[ring_slot<P>(k2)]);
+        if (k1 >= 0 && k1 < c0 + nc) w = (double)L.nrm2[ring_slot_of<RB>(k1)];
+        if (lane < nc) w = fmax(w, (double)L.nrm2[ring_slot_of<RB>(k2)]);
         const double cmax2 = wave_max(w) * dymax2;
         int qq = 0;
 #pragma unroll
@@ -358,12 +363,12 @@ struct StripCtx {
     // is recomputed after load_chunk().
     static constexpr bool kAhead = P <= 8;
     __device__ __forceinline__ void prefetch(int t) {
-        const int ri = ring_slot<P>(t - lane_id());
+        const int ri = ring_slot_of<RB>(t - lane_id());
         double c0 = 0.0, c1 = 0.0;
 #pragma unroll
         for (int ch = 0; ch < D; ch += 2) {
-            c0 = fma(dy[ch], L.dx[ch * ring_cols(P) + ri], c0);
-            c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ring_cols(P) + ri], c1);
+            c0 = fma(dy[ch], L.dx[ch * RB + ri], c0);
+            c1 = fma(dy[ch + 1], L.dx[(ch + 1) * RB + ri], c1);
         }
         cn = c0 + c1;
     }
@@ -385,9 +390,9 @@ struct StripCtx {
             if constexpr (kAhead) {
                 // increments of the next step's column, consumed after the map
                 c = cn;
-                const int ri = ring_slot<P>(t + 1 - lane);
+                const int ri = ring_slot_of<RB>(t + 1 - lane);
 #pragma unroll
-                for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * ring_cols(P) + ri];
+                for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * RB + ri];
             } else {
                 prefetch(t);
                 c = cn;
