@@ -8,8 +8,8 @@
 // top-edge series it produces moves to lane j+1 for the next step by a DPP
 // wave shift.  Lane 0 takes its bottom edge from the frontier row written by
 // the strip below; lane 63 writes its top edge to the frontier for the strip
-// above.  Frontier columns are exchanged between strips in chunks (64
-// columns for orders up to 5 at 8 channels, else 32):
+// above.  Frontier columns are exchanged between strips in chunks (32 or 64
+// columns, a template parameter chosen per variant and sweep):
 // lane 63's edges are staged in LDS and written out with device-coherent
 // stores, followed by a progress flag per strip; the strip above polls the
 // flag and reads the chunk with device-coherent loads (no cache maintenance).
