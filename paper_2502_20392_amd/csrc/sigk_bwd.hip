@@ -27,9 +27,16 @@
 
 namespace sigk {
 
+// Frontier chunk of the checkpointing forward sweep (which also sets the
+// granularity of the Neumann depths the adjoint reads back): 64 columns where
+// the kernel runs one wave per SIMD anyway (orders 10-20, D <= 16), as in the
+// plain forward sweep; 32 elsewhere.
+template <int P, int D>
+constexpr int ckpt_chunk = (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
+
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
-    constexpr int CH = chunk_cols(P), RB = ring_cols(P);
+    constexpr int CH = ckpt_chunk<P, D>, RB = CH == 64 ? 128 : ring_cols(P);
     __shared__ LdsStrip<P, D, CH, RB> L;
     Acc acc;
     const int lane = lane_id();
@@ -189,7 +196,7 @@ struct StripBwd {
     }
 
     __device__ __forceinline__ int depth_at(int t) const {
-        const int CKCH = chunk_cols(P);
+        const int CKCH = ckpt_chunk<P, D>;
         const int k = min(t, m - 1) / CKCH;
         return uniform((int)ckq[k]);
     }
