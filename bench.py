@@ -199,7 +199,7 @@ def mmd(torch, sk, dev, synth, res):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "libsigk runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
