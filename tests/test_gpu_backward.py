@@ -49,6 +49,27 @@ def test_pair_gradient_vs_oracle(dev, lx, ly):
     assert sk().counters()["status"] == 0
 
 
+@pytest.mark.parametrize("order", [5, 10, 12, 16, 20])
+def test_gradient_several_chunks(dev, order):
+    """A pair spanning several frontier chunks and a partial one (299 columns,
+    199 rows, 4 strips), at orders whose sweeps use 64-column chunks (the plain
+    forward at 5 and 10-20, the checkpointing sweep at 10-20, the adjoint at 10
+    and 12) and at one that does not, against the oracle's value and gradient.
+    Order 5 gets smaller steps (cell increments up to 5e-5), for which its
+    series' last kept coefficient stays under the tail tolerance."""
+    g = synth.rng(4200 + order)
+    step = 0.002 if order < 10 else 0.01
+    x = np.cumsum(g.normal(size=(300, 3)) * step, axis=0)
+    y = np.cumsum(g.normal(size=(200, 3)) * step, axis=0)
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=order)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-12 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-10 * sc
+    assert np.abs(gy - gy0).max() <= 1e-10 * sc
+    assert sk().counters()["status"] == 0
+
+
 def test_weighted_batch_shared_paths(dev):
     """Several pairs sharing paths, weighted: gradient is sum_p w_p grad k_p."""
     pool, off, _ = synth.ragged_paths(n_paths=5, lmin=20, lmax=90, d=4, smin=0.3, smax=0.6)
