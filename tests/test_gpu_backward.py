@@ -49,18 +49,19 @@ def test_pair_gradient_vs_oracle(dev, lx, ly):
     assert sk().counters()["status"] == 0
 
 
+@pytest.mark.parametrize("d", [3, 8])
 @pytest.mark.parametrize("order", [5, 10, 12, 16, 20])
-def test_gradient_several_chunks(dev, order):
+def test_gradient_several_chunks(dev, order, d):
     """A pair spanning several frontier chunks and a partial one (299 columns,
     199 rows, 4 strips), at orders whose sweeps use 64-column chunks (the plain
     forward at 5 and 10-20, the checkpointing sweep at 10-20, the adjoint at 10
     and 12) and at one that does not, against the oracle's value and gradient.
     Order 5 gets smaller steps (cell increments up to 5e-5), for which its
     series' last kept coefficient stays under the tail tolerance."""
-    g = synth.rng(4200 + order)
-    step = 0.002 if order < 10 else 0.01
-    x = np.cumsum(g.normal(size=(300, 3)) * step, axis=0)
-    y = np.cumsum(g.normal(size=(200, 3)) * step, axis=0)
+    g = synth.rng(4200 + 10 * order + d)
+    step = (0.002 if order < 10 else 0.01) * np.sqrt(3 / d)
+    x = np.cumsum(g.normal(size=(300, d)) * step, axis=0)
+    y = np.cumsum(g.normal(size=(200, d)) * step, axis=0)
     k0, gx0, gy0 = oracle.grad(x, y)
     k, gx, gy = gpu_pair_grad(x, y, dev, order=order)
     sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
