@@ -71,6 +71,44 @@ def test_gradient_several_chunks(dev, order, d):
     assert sk().counters()["status"] == 0
 
 
+def test_degenerate_paths_in_gradient_batch(dev):
+    """A ragged batch mixing paths of 0, 1 and 2 points with longer ones: pairs
+    with a path of at most one point have k = 1 and contribute nothing to the
+    gradient (a one-point path's gradient is exactly 0); the rest match the
+    oracle, weighted."""
+    g = synth.rng(4300)
+    d = 3
+    paths = [np.cumsum(g.normal(size=(50, d)) * 0.05, axis=0), g.normal(size=(1, d)),
+             np.zeros((0, d)), np.cumsum(g.normal(size=(40, d)) * 0.05, axis=0),
+             np.cumsum(g.normal(size=(2, d)) * 0.05, axis=0)]
+    lens = [len(p) for p in paths]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pool = np.concatenate(paths)
+    pairs = np.array([[0, 1], [1, 0], [2, 3], [0, 3], [4, 3], [1, 2]], dtype=np.int32)
+    w = np.array([0.7, -1.3, 2.0, 0.9, -0.4, 1.1])
+    plan = sk().RaggedPlan(off, pairs, d, order=16, device=dev)
+    pd = T(pool, dev)
+    kv = plan.run(pd).cpu().numpy()
+    assert sk().counters()["status"] == 0
+    gp = plan.backward(pd, T(w, dev)).cpu().numpy()
+    assert sk().counters()["status"] == 0
+    k03, gx03, gy03 = oracle.grad(paths[0], paths[3])
+    k43, gx43, gy43 = oracle.grad(paths[4], paths[3])
+    assert np.all(kv[[0, 1, 2, 5]] == 1.0)
+    assert abs(kv[3] - k03) <= 1e-12 * max(1, abs(k03))
+    assert abs(kv[4] - k43) <= 1e-12 * max(1, abs(k43))
+    ref = [w[3] * gx03, np.zeros((1, d)), np.zeros((0, d)), w[3] * gy03 + w[4] * gy43,
+           w[4] * gx43]
+    sc = max(1.0, max(np.abs(r).max() for r in ref if r.size))
+    for i, r in enumerate(ref):
+        got = gp[off[i]:off[i + 1]]
+        assert got.shape == r.shape
+        if i == 1:
+            assert not np.any(got)
+        else:
+            assert np.abs(got - r).max(initial=0.0) <= 1e-10 * sc, i
+
+
 def test_weighted_batch_shared_paths(dev):
     """Several pairs sharing paths, weighted: gradient is sum_p w_p grad k_p."""
     pool, off, _ = synth.ragged_paths(n_paths=5, lmin=20, lmax=90, d=4, smin=0.3, smax=0.6)
