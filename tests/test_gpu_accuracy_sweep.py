@@ -1,6 +1,7 @@
-"""Accuracy against the edge order on two-dimensional Brownian motion.
+"""Accuracy against the edge order on two-dimensional Brownian motion and
+fractional Brownian motion.
 
-Paths of 2^k + 1 points on [0, 1] (quadratic variation sigma^2 per channel),
+Brownian paths of 2^k + 1 points on [0, 1] (quadratic variation sigma^2 per channel),
 k(x, y) at every compiled edge order against the oracle.  What truncation
 promises (the edge series of Sec. 3 cut at P terms, the device tail check
 flagging a last kept coefficient above the tail tolerance): every result
@@ -60,3 +61,29 @@ def test_order_sweep_brownian_2d(dev, length, sigma):
     assert sk().counters()["status"] == 0
     assert abs(ka - ref) <= bar * max(1.0, abs(ref))
     assert sk().counters()["order"] == first
+
+
+@pytest.mark.parametrize("hurst", [0.4, 0.2, 0.1, 0.05, 0.01, 0.005])
+def test_order_sweep_fbm_2d(dev, hurst):
+    """2-D fractional Brownian motion of 51 points, quadratic variation 1 per
+    channel, Hurst exponent from 0.4 down to 0.005 (rougher and rougher at the
+    same variation): the same promises as above, bar 1e-10."""
+    X = synth.fbm_paths(2, 51, 2, hurst, seed=5100 + int(1000 * hurst))
+    ref = oracle.pair(X[0], X[1])
+    x = torch.from_numpy(X[0]).to(dev)
+    y = torch.from_numpy(X[1]).to(dev)
+    orders = sk()._lib.ORDERS
+    errs, flags = {}, {}
+    for p in orders:
+        k = sk().pair(x, y, order=p).item()
+        flags[p] = sk().counters()["status"]
+        errs[p] = abs(k - ref) / max(1.0, abs(ref))
+        assert np.isfinite(k), (p, k)
+        assert not flags[p] & ~sk()._lib.WARN_TRUNC, (p, flags[p])
+    print(f"\nfBM H {hurst} k {ref:.6g}: " +
+          " ".join(f"P{p}:{errs[p]:.1e}{'w' if flags[p] else ''}" for p in orders))
+    for p in orders:
+        if flags[p] == 0:
+            assert errs[p] <= 1e-10, (hurst, p, errs[p])
+    assert flags[orders[-1]] == 0, hurst
+    assert errs[orders[-1]] <= 1e-12, (hurst, errs[orders[-1]])
