@@ -148,3 +148,19 @@ def test_deterministic(dev):
     a = sk().pair(T(X[0], dev), T(X[1], dev), order=10).item()
     b = sk().pair(T(X[0], dev), T(X[1], dev), order=10).item()
     assert a == b
+
+
+@pytest.mark.parametrize("sigma", [1.0, 3.0])
+def test_gram_positive_semidefinite(dev, sigma):
+    """The GPU Gram of 24 Brownian paths (length 200, d 4) is symmetric
+    positive semi-definite and obeys Cauchy-Schwarz, as an inner product of
+    signatures must (Definition 2.1)."""
+    X = synth.brownian(24, 200, 4, sigma, seed=900 + int(sigma))
+    G = sk().gram(T(X, dev), order="auto").cpu().numpy()
+    assert sk().counters()["status"] == 0
+    assert np.array_equal(G, G.T)
+    ev = np.linalg.eigvalsh(G)
+    assert ev.min() >= -1e-10 * ev.max(), ev[:3]
+    dg = np.diag(G)
+    assert np.all(dg > 0)
+    assert np.all(G * G <= np.outer(dg, dg) * (1 + 1e-10))

@@ -239,3 +239,19 @@ def test_gram_and_ragged_consistent():
         for j in range(4):
             assert G[i, j] == oracle.pair(X[i], X[j]) or rel(G[i, j], oracle.pair(X[i], X[j])) < 1e-13
     np.testing.assert_allclose(G, G.T, rtol=1e-13)
+
+
+@pytest.mark.parametrize("sigma", [0.5, 2.0])
+def test_gram_positive_semidefinite(sigma):
+    """k is the inner product of the signatures of the piecewise-linear paths
+    (Definition 2.1), so every Gram matrix is symmetric positive semi-definite
+    and k(x, y)^2 <= k(x, x) k(y, y); a sign or index slip in the cell map
+    breaks this for some family."""
+    X = synth.brownian(8, 24, 2, sigma, seed=77 + int(10 * sigma))
+    G = oracle.gram(X)
+    np.testing.assert_allclose(G, G.T, rtol=1e-13)
+    ev = np.linalg.eigvalsh(G)
+    assert ev.min() >= -1e-12 * ev.max(), ev
+    dg = np.diag(G)
+    assert np.all(dg > 0)
+    assert np.all(G * G <= np.outer(dg, dg) * (1 + 1e-12))
