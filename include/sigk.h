@@ -115,6 +115,25 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
               int64_t d, int symmetric, const sigk_opts* o, double* G, void* ws,
               size_t ws_bytes, void* stream);
 
+/*
+ * sigk_gram without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP-graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, values and kernels as sigk_gram
+ * (sigk_pair is its 1 x 1 case); the workspace is a file-scope device array of
+ * SIGK_STATIC_WS_BYTES held by every device the library runs on until the
+ * process ends.  Calls that would need more return SIGK_EWORKSPACE before
+ * any device work.  The call allocates nothing (no hipMalloc, no hipFree, no
+ * allocating library routine) and is asynchronous on `stream`.
+ *   status (device, optional): receives the call's SIGK_WARN_* / SIGK_ERR_*
+ *          bits, written on `stream` after the launch (NULL: not reported).
+ * All calls on one device share the array: calls that overlap on a device
+ * (other streams, unordered host threads) race and give undefined results.
+ */
+#define SIGK_STATIC_WS_BYTES (64u << 20)
+int sigk_gram_static(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t lx,
+                     int64_t ly, int64_t d, int symmetric, const sigk_opts* o, double* G,
+                     uint32_t* status, void* stream);
+
 /* ---------------------------------------------------------------- ragged batch */
 /*
  * A plan describes a ragged batch of pairs of paths of different lengths

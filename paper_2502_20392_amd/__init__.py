@@ -2,6 +2,6 @@
 (arXiv 2502.20392).  The compute path is libsigk.so (hand-written HIP for
 gfx950) behind the C ABI of include/sigk.h; this package is its Python
 binding (PyTorch for device memory and streams) plus autograd wrappers."""
-from .api import (RaggedPlan, backward, counters, gram, gram_ragged, last_workspace,  # noqa: F401
-                  mmd2, pair, ragged, sigkernel_gram, workspace)
+from .api import (RaggedPlan, backward, counters, gram, gram_ragged, gram_static,  # noqa: F401
+                  last_workspace, mmd2, pair, ragged, sigkernel_gram, workspace)
 from . import _lib  # noqa: F401

@@ -23,6 +23,8 @@ ERR_WATCHDOG = 4
 
 FLAG_FIXED_DEPTH = 1
 
+STATIC_WS_BYTES = 64 << 20  # SIGK_STATIC_WS_BYTES
+
 ORDERS = (4, 5, 6, 8, 10, 12, 16, 20, 24)
 BWD_ORDERS = (4, 5, 6, 8, 10, 12, 16, 20, 24)
 
@@ -64,6 +66,8 @@ SIGNATURES = {
                                                 ctypes.POINTER(Opts), ctypes.POINTER(_SZ)]),
     "sigk_gram": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _I64, _I64, ctypes.c_int,
                                  ctypes.POINTER(Opts), _P, _P, _SZ, _P]),
+    "sigk_gram_static": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _I64, _I64, ctypes.c_int,
+                                        ctypes.POINTER(Opts), _P, _P, _P]),
     "sigk_plan_ragged": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, ctypes.POINTER(Opts),
                                         ctypes.POINTER(_P)]),
     "sigk_plan_destroy": (None, [_P]),

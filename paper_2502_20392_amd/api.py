@@ -9,6 +9,7 @@ stream; every arithmetic step runs in libsigk's HIP kernels.  Paths are
 * ``RaggedPlan``            a ragged batch of path pairs: one persistent launch,
                             graph-capturable ``run``, and ``backward``.
 * ``ragged(pool, offsets, pairs)``  one-shot ragged batch.
+* ``gram_static(X, Y)``     Gram matrix through the library's static workspace.
 * ``counters(ws)``          cells, algorithmic flops and status of a call.
 
 ``order`` is the number of coefficients kept per edge series (P).  With
@@ -172,6 +173,27 @@ def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False
         return G, w
 
     return _auto(run, order, order_hint)
+
+
+def gram_static(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False,
+                status=None):
+    """sigk_gram_static: the Gram matrix through the library's static device
+    workspace (no workspace allocation; see include/sigk.h).  ``status``: an
+    optional int32 CUDA tensor of one element that receives the status bits."""
+    X = _check_paths(X, "X", 3)
+    sym = Y is None
+    Y = X if sym else _check_paths(Y, "Y", 3)
+    if X.shape[2] != Y.shape[2]:
+        raise ValueError("X and Y must have the same number of channels")
+    nx, lx, d = X.shape
+    ny, ly, _ = Y.shape
+    if status is not None:
+        _check_buffer(status, "status", 1, X.device, dtype=torch.int32, exact=True)
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
+    _lib.check(_lib.load().sigk_gram_static(_ptr(X), nx, _ptr(Y), ny, lx, ly, d, int(sym),
+                                            ctypes.byref(o), _ptr(G), _ptr(status), _stream()))
+    return G
 
 
 class RaggedPlan:

@@ -62,7 +62,7 @@ def _compile(src, obj, defs, force):
 
 def build(force: bool = False, jobs: int = 0, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    units = [("sigk_api.hip", "api.o", [])]
+    units = [("sigk_api.hip", "api.o", []), ("sigk_static.hip", "static.o", [])]
     for p, d in _variants("SIGK_FWD_VARIANTS"):
         units.append(("sigk_fwd.hip", f"fwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
     for p, d in _variants("SIGK_BWD_VARIANTS"):

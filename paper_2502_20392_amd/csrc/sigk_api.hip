@@ -157,11 +157,6 @@ hipError_t launch_reset(WsHeader* h, int* prog, int64_t nprog, double* out, int6
 
 thread_local char g_errbuf[256];
 
-int device_error(hipError_t e) {
-    std::snprintf(g_errbuf, sizeof g_errbuf, "HIP error: %s", hipGetErrorString(e));
-    return SIGK_EDEVICE;
-}
-
 // ---------------------------------------------------------------- gram layout
 struct GramLayout {
     size_t hdr = 0, prog = 0, front = 0, total = 0;
@@ -182,6 +177,13 @@ GramLayout gram_layout(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int symme
 }
 
 }  // namespace
+
+namespace sigk {
+int device_error(hipError_t e) {
+    std::snprintf(g_errbuf, sizeof g_errbuf, "HIP error: %s", hipGetErrorString(e));
+    return SIGK_EDEVICE;
+}
+}  // namespace sigk
 
 // ===================================================================== plan
 struct sigk_plan {

@@ -129,6 +129,9 @@ struct BwdArgs {
     double* scratch;         // per workgroup: kCkptEvery x P x 64 recomputed bottom edges
 };
 
+// Records the HIP error string for sigk_strerror and returns SIGK_EDEVICE.
+int device_error(hipError_t e);
+
 // Launchers implemented per variant (one translation unit each).
 #define SIGK_DECL_FWD(P, D) \
     hipError_t launch_fwd_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
