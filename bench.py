@@ -31,8 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
-FIRST_ORDER = 4  # order search for the headline pair starts here
-MMD_FIRST_ORDER = 8  # and for the MMD^2 workload
+FIRST_ORDER = 4  # every order search starts at the smallest compiled order
 METRIC = "Goursat grid cells/s (fwd, fwd+bwd) at rel err ≤1e-10 vs FP64 oracle"
 
 
@@ -48,6 +47,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=0.0, help="Neumann tolerance (0: by size)")
     ap.add_argument("--cpu-sample", type=int, default=7001,
                     help="points of the prefix pair the CPU oracle evaluates")
+    ap.add_argument("--cpu-batch-pairs", type=int, default=64,
+                    help="pairs of the 64 x 64 Gram the threaded CPU oracle evaluates")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="",
@@ -131,18 +132,50 @@ def extras(torch, sk, dev, only=""):
         c = sk.counters()
         res[name] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": order,
                      "orders_tried": tried, "fp64_frac": frac(c["flops"], ms),
-                     "status": c["status"]}
+                     "status": c["status"], "trunc_est": c["trunc_est"]}
 
     for name, sig in (("gram64_len1024_d16_sigma1", 1.0), ("gram64_len1024_d16_sigma4", 4.0)):
         if want(name):
-            gram_entry(name, torch.from_numpy(synth.gram_mid(sig)).to(dev), 8)
+            gram_entry(name, torch.from_numpy(synth.gram_mid(sig)).to(dev), FIRST_ORDER)
     if want("gram8_len128_d3"):
-        gram_entry("gram8_len128_d3", torch.from_numpy(synth.gram_small()).to(dev), 4)
+        gram_entry("gram8_len128_d3", torch.from_numpy(synth.gram_small()).to(dev), FIRST_ORDER)
     if want("ragged512_len64to4096_d32_graph"):
         ragged(torch, sk, dev, synth, tune, frac, res)
     if want("mmd_32x32_len2048_d8_fwd_bwd"):
         mmd(torch, sk, dev, synth, res)
+    if want("dim_sweep_len4096"):
+        dim_sweep(torch, sk, dev, synth, frac, res)
     return res
+
+
+def dim_sweep(torch, sk, dev, synth, frac, res):
+    """Runtime against the number of channels (the paper's dimension
+    experiment): one pair of length 4096, d = 2 ... 8192, Brownian increments
+    N(0, 1/(d (len-1))) per channel (total quadratic variation 1 whatever d);
+    d > 32 takes the matrix-core field stage.  Each d at the smallest compiled
+    order whose run raises no truncation warning."""
+    from paper_2502_20392_amd import _lib
+    rows = []
+    for d in (2, 8, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        X = synth.brownian(2, 4096, d, 1.0 / np.sqrt(d), seed=9000 + d)
+        x = torch.from_numpy(X[0]).to(dev)
+        y = torch.from_numpy(X[1]).to(dev)
+        del X
+        for order in [p for p in _lib.ORDERS if p >= FIRST_ORDER]:
+            sk.pair(x, y, order=order)
+            st = sk.counters()["status"]
+            if not st & _lib.WARN_TRUNC:
+                break
+        ms = timed(lambda: sk.pair(x, y, order=order), torch)
+        c = sk.counters()
+        rows.append({"d": d, "order": order, "ms": ms, "cells_per_s": c["cells"] / (ms / 1e3),
+                     "fp64_frac": frac(c["flops"], ms), "status": c["status"]})
+        print(f"# dim sweep d {d}: order {order} {ms:.2f} ms", file=sys.stderr, flush=True)
+        del x, y
+        torch.cuda.empty_cache()
+    res["dim_sweep_len4096"] = {"rows": rows,
+                                "note": "d > 32: cell coefficients from the FP64 matrix-core "
+                                        "stage; fp64_frac counts its 2d flops per cell"}
 
 
 def ragged(torch, sk, dev, synth, tune, frac, res):
@@ -170,7 +203,7 @@ def mmd(torch, sk, dev, synth, res):
     # edge order: the smallest compiled order from MMD_FIRST_ORDER up whose
     # forward blocks (XX, YY, XY) raise no truncation warning (untimed)
     tried = []
-    for order in [p for p in _lib.ORDERS if p >= MMD_FIRST_ORDER]:
+    for order in [p for p in _lib.BWD_ORDERS if p >= FIRST_ORDER]:
         st = 0
         for A, B in ((Xt.detach(), None), (Yt, None), (Xt.detach(), Yt)):
             sk.gram(A, B, order=order)
@@ -180,20 +213,66 @@ def mmd(torch, sk, dev, synth, res):
             break
 
     def fb():
+        # check=True: the autograd calls read the device status of their own
+        # launches (the timed ones) after the forward and after the backward
         Xt.grad = None
-        sk.mmd2(Xt, Yt, order=order).backward()
+        sk.mmd2(Xt, Yt, order=order, check=True).backward()
 
     ms = timed(fb, torch, steps=2)
+    tally = sk.last_autograd_counters()
     nx, lx = Xm.shape[0], Xm.shape[1]
     ny, ly = Ym.shape[0], Ym.shape[1]
     fwd_cells = (nx * (nx + 1) // 2 * (lx - 1) ** 2 + ny * (ny + 1) // 2 * (ly - 1) ** 2
                  + nx * ny * (lx - 1) * (ly - 1))
     bwd_cells = nx * (nx + 1) // 2 * (lx - 1) ** 2 + nx * ny * (lx - 1) * (ly - 1)
+    assert tally["cells"] == fwd_cells and tally["bwd_cells"] == bwd_cells, tally
     res["mmd_32x32_len2048_d8_fwd_bwd"] = {
         "cells_per_s": fwd_cells / (ms / 1e3), "ms": ms, "order": order,
-        "orders_tried": tried, "status": st,
+        "orders_tried": tried, "status": tally["status"], "trunc_est": tally["trunc_est"],
         "fwd_cells": fwd_cells, "bwd_cells": bwd_cells,
-        "note": "fwd+bwd: forward cells over the time of forward plus backward"}
+        "fwd_flops": tally["flops"], "bwd_flops": tally["bwd_flops"],
+        "fp64_frac": (tally["flops"] + tally["bwd_flops"]) / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+        "note": "fwd+bwd: forward cells over the time of forward plus backward; status and "
+                "flops of the timed run (forward sweeps and adjoint sweep, counted on the "
+                "device)"}
+
+
+def host_info():
+    """CPUs this process may use and the CPU model (Linux)."""
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except Exception:
+        cpus = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return {"cpus": cpus, "model": model}
+
+
+def batch_oracle(npairs, threads):
+    """The oracle's thread pool on a seeded subset of the 64 x 64 Gram (length
+    1024, d 16, sigma 1): the first `npairs` pairs of its upper triangle."""
+    import oracle
+    import synth
+    X = synth.gram_mid(1.0)
+    nx, lx, d = X.shape
+    ii, jj = np.triu_indices(nx)
+    pairs = np.stack([ii, jj], 1)[:npairs].astype(np.int32)
+    pool = X.reshape(-1, d)
+    offsets = np.arange(nx + 1, dtype=np.int64) * lx
+    t0 = time.perf_counter()
+    oracle.ragged(pool, offsets, pairs, nthreads=threads)
+    dt = time.perf_counter() - t0
+    cells = len(pairs) * (lx - 1) ** 2
+    return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(pairs)} pairs of the upper triangle of the 64 x 64 Gram "
+                      f"(length 1024, d 16, sigma 1, seed 2): {cells:.3e} cells in {dt:.1f} s "
+                      f"on {threads} threads (one pair per thread)"}
 
 
 def main():
@@ -286,6 +365,7 @@ def main():
                    "cells_per_step": cells},
         "k": kk.item(),
         "status": cnt["status"],
+        "trunc_est": cnt["trunc_est"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": f"fwd_kernel<{cnt['order']}, 8>",
@@ -308,11 +388,14 @@ def main():
         scells = (n - 1) ** 2
         kg = sk.pair(torch.from_numpy(xs).to(dev), torch.from_numpy(ys).to(dev),
                      order=args.order).item()
+        host = host_info()
         out["cpu_baseline"] = {"value": scells / cs, "unit": "cells/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"prefix pair {n}x{n} points of the same workload "
                                          f"({scells:.3e} cells, {cs:.1f} s); one thread: the "
-                                         f"raster sweep of one pair is sequential"}
+                                         f"raster sweep of one pair is sequential",
+                               "host_cpus": host["cpus"], "cpu_model": host["model"],
+                               "batch": batch_oracle(args.cpu_batch_pairs, host["cpus"])}
         out["parity_sample"] = {"sample": f"prefix {n}x{n}", "gpu": kg, "oracle": kref,
                                 "rel_err": abs(kg - kref) / max(abs(kref), 1.0)}
     print(json.dumps(out))

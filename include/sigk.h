@@ -16,10 +16,14 @@
  *
  * Method (Prop. 2.5, Prop. 2.8).  Each cell's solution is a local power
  * series; the boundary series (top and right edges) of each cell feed the
- * next cells along the tile DAG in topological (anti-diagonal) order.  Per
- * cell, the Neumann series is cut adaptively once the next term is below
- * `tol` relative to the edge data (Sec. C.3: "stops once the next term is
- * below machine precision"); the edge series keep `order` coefficients.
+ * next cells along the tile DAG in topological (anti-diagonal) order.  The
+ * Neumann series of a cell is cut adaptively: its terms are dropped once
+ * their bound falls under `tol` relative to the edge data (the per-tile
+ * stopping rule of App. B, with a tolerance scaled to the pair's size).  The
+ * edge series keep `order` coefficients; the error this drops is estimated
+ * cell by cell and summed over each pair (the local truncation error of
+ * App. C, "Error Analysis and Limitations"), and a pair whose estimate
+ * exceeds its budget raises SIGK_WARN_TRUNC.
  *
  * Conventions for every entry point below:
  *   - All array pointers are DEVICE pointers unless marked "host".
@@ -53,14 +57,26 @@ extern "C" {
 #define SIGK_EUNSUPPORTED (-4) /* order or dimension outside the compiled range  */
 
 /* device status bits (sigk_read_status) */
-#define SIGK_WARN_TRUNC 1u     /* an edge series' last kept coefficient exceeded
-                                  tail_tol relative to the edge norm: raise order */
+#define SIGK_WARN_TRUNC 1u     /* a pair's estimated truncation error exceeded
+                                  its budget (tail_tol): raise the order        */
 #define SIGK_WARN_NONFINITE 2u /* NaN or Inf produced                              */
 #define SIGK_ERR_WATCHDOG 4u   /* a dependency wait exceeded its time limit; the
                                   results of that call are invalid                */
+#define SIGK_ERR_TABLE 8u      /* a device pair table named a path id out of range,
+                                  an offset outside the pool or a path longer than
+                                  max_len: those pairs are skipped (value NaN, no
+                                  gradient)                                       */
 
 /* flags */
 #define SIGK_FLAG_FIXED_DEPTH 1u /* no adaptive Neumann depth: all order-1 terms  */
+#define SIGK_FLAG_SQUARE 2u      /* square truncation of every tile's coefficient
+                                    matrix, 0 <= i, j <= N = order-1: the fixed-
+                                    order approximant of App. C and Prop. A.3.
+                                    With SIGK_FLAG_FIXED_DEPTH and order 8 it is
+                                    the paper's default fixed order N = 7 (Sec. 3).
+                                    Compiled for order 8, forward calls only;
+                                    other orders and the adjoint return
+                                    SIGK_EUNSUPPORTED.                          */
 
 typedef struct sigk_opts {
     double tol;        /* Neumann-depth tolerance per cell: term n is skipped for
@@ -68,8 +84,11 @@ typedef struct sigk_opts {
                           a chunk.  These per-cell bounds add up over the cells
                           of a pair, so <= 0 selects min(2^-53, 2^-36/cells) with
                           cells = (lx-1)(ly-1) of the largest pair of the call.   */
-    double tail_tol;   /* truncation warning threshold for the last edge
-                          coefficient relative to the edge norm; <= 0: 2^-50.     */
+    double tail_tol;   /* budget of a pair's estimated relative truncation error:
+                          the sum over its cells of |c| (|A'_{P-1}| + |B'_{P-1}|)/P!
+                          (the leading dropped coefficient of both output edges,
+                          in the derivative basis) relative to the local size of
+                          K; above it SIGK_WARN_TRUNC is raised.  <= 0: 2^-36.   */
     int32_t order;     /* P = coefficients kept per edge series (degree P-1);
                           0 selects 12.  Rounded up to a compiled value
                           (4,5,6,8,10,12,16,20,24).                               */
@@ -84,10 +103,20 @@ typedef struct sigk_counters {
                        (FMA = 2), including the increment inner products     */
     uint32_t status;
     uint32_t order; /* compiled edge order P used by the last call          */
+    double trunc_est; /* largest per-pair truncation estimate (see tail_tol) of
+                         the last forward sweep                              */
+    uint64_t bwd_cells; /* cells of the last adjoint sweep                     */
+    uint64_t bwd_flops; /* its algorithmic FP64 flops: adjoint cell maps, the
+                           forward maps they recompute, dL/dc and its chain to
+                           both increments (FMA = 2)                         */
 } sigk_counters;
 
-/* Default options (tol by size, tail_tol 2^-50, order 12). host */
+/* Default options (tol by size, tail_tol 2^-36, order 12). host */
 void sigk_default_opts(sigk_opts* o);
+
+#define SIGK_FLAG_FIELD 4u /* compute the cell coefficients of a pair or Gram
+                              call with the matrix-core field stage even for
+                              d <= 32 (it is always used for d > 32)          */
 
 /* ---------------------------------------------------------------- one pair */
 /*
@@ -99,6 +128,11 @@ int sigk_pair_workspace_size(int64_t lx, int64_t ly, int64_t d, const sigk_opts*
 /*
  * k(x, y) for one pair (Definition 2.1).  x: [lx][d], y: [ly][d] row-major
  * FP64; k_out: one double.  Any lx, ly >= 0 (fewer than 2 points: k = 1).
+ * Any d >= 1: up to d = 32 the cell coefficients <dx_k, dy_l> are formed in
+ * the sweep; for d > 32 (or with SIGK_FLAG_FIELD) they are computed first on
+ * the FP64 matrix cores as the product of the two increment sequences and
+ * stored in the workspace, (lx + 63) x 64 doubles per 64 rows of y (the
+ * ragged plans, the one-call ragged forms and the adjoint take d <= 32).
  */
 int sigk_pair(const double* x, int64_t lx, const double* y, int64_t ly, int64_t d,
               const sigk_opts* o, double* k_out, void* ws, size_t ws_bytes, void* stream);
@@ -168,17 +202,32 @@ int sigk_plan_upload(const sigk_plan* plan, void* ws, size_t ws_bytes, void* str
 int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* ws,
                   size_t ws_bytes, void* stream);
 /*
- * Convenience: plan + upload + run in one call (synchronous with respect to
- * the host for the table copy; not capturable).  offsets and pairs are host
- * arrays as for sigk_plan_ragged.
+ * One-call ragged batch on DEVICE tables (Proposition A.3's Gram entries for
+ * an arbitrary list of pairs of paths of different lengths, Definition 2.1
+ * for each): out[p] = k(path pairs[p][0], path pairs[p][1]).
+ *   pool (device) [pool_points][d]: the paths back to back;
+ *   offsets (device) [npaths+1]: first point of each path in the pool;
+ *   pairs (device) [npairs][2]: path ids of each pair;
+ *   max_len: an upper bound on the points of every path a pair names (host
+ *            scalar; it sizes the workspace: every pair is laid out for paths
+ *            of max_len points);
+ *   out (device) [npairs].
+ * The descriptor and ticket tables are built on the device by small kernels
+ * before the persistent launch, so the call allocates nothing, copies nothing
+ * from the host, never synchronises and can be captured in a HIP graph.
+ * Pairs whose table entries are invalid (path id out of range, offsets
+ * decreasing or outside [0, pool_points], a path longer than max_len) get
+ * out = NaN and raise SIGK_ERR_TABLE; the others are computed normally.
+ * ws: at least sigk_gram_ragged_workspace_size bytes (host, from the same
+ * scalars).
  */
-int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
-                     const int32_t* pairs, int64_t npairs, const sigk_opts* o, double* out,
-                     void* ws, size_t ws_bytes, void* stream);
-/* Workspace bytes for sigk_gram_ragged (host; host offsets and pairs). */
-int sigk_gram_ragged_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
-                                    const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+int sigk_gram_ragged_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,
+                                    int64_t pool_points, int64_t d, const sigk_opts* o,
                                     size_t* bytes);
+int sigk_gram_ragged(const double* pool, int64_t pool_points, const int64_t* offsets,
+                     int64_t npaths, int64_t d, const int32_t* pairs, int64_t npairs,
+                     int64_t max_len, const sigk_opts* o, double* out, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* ---------------------------------------------------------------- adjoint */
 /*
@@ -211,19 +260,56 @@ int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
                                     size_t ws_bytes, void* stream);
 
 /*
- * Convenience: plan + upload + sigk_plan_backward in one call for a ragged
- * batch (the gradient of L = sum_p grad_out[p] k(pair p) with respect to the
- * pool, ACCUMULATED into grad_pool).  offsets and pairs are host arrays as for
- * sigk_plan_ragged; synchronous with respect to the host (the plan's tables
- * are copied from host memory); not capturable.  ws: at least
+ * Gradient of L = sum_p grad_out[p] * k(pair p) with respect to the pool, on
+ * DEVICE tables as for sigk_gram_ragged (same arguments and validation), in
+ * one asynchronous call: grad_pool[i][c] += dL/dpool[i][c] (ACCUMULATED).
+ * dk/dpool follows from the Volterra form of the Goursat problem (Sec. 2.1):
+ * the derivative of K(1, 1) with respect to the coefficient of a cell is the
+ * integral over the cell of K times the solution of the adjoint (reversed)
+ * problem; it is evaluated here as the exact adjoint of the truncated cell
+ * maps, swept in reverse wavefront order over checkpoints of a forward sweep,
+ * then chained through c_kl = <dx_k, dy_l> and dx_k = x_{k+1} - x_k.
+ *   grad_out (device) [npairs]; grad_pool (device) [pool_points][d].
+ * Allocates nothing, never synchronises, capturable; invalid pairs raise
+ * SIGK_ERR_TABLE and contribute no gradient.  ws: at least
  * sigk_backward_workspace_size bytes.
  */
-int sigk_backward_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
-                                 const int32_t* pairs, int64_t npairs, const sigk_opts* o,
+int sigk_backward_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,
+                                 int64_t pool_points, int64_t d, const sigk_opts* o,
                                  size_t* bytes);
-int sigk_backward(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
-                  const int32_t* pairs, int64_t npairs, const double* grad_out, const sigk_opts* o,
-                  double* grad_pool, void* ws, size_t ws_bytes, void* stream);
+int sigk_backward(const double* pool, int64_t pool_points, const int64_t* offsets,
+                  int64_t npaths, int64_t d, const int32_t* pairs, int64_t npairs,
+                  int64_t max_len, const double* grad_out, const sigk_opts* o, double* grad_pool,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- order estimate */
+/*
+ * A-priori truncation order (App. C, "Error Analysis and Limitations": the
+ * tile matrix at the largest cell coefficient, its last row and column summed
+ * and scaled to the cell size, searched over N).  Reading taken here: with
+ * cmax the largest |<dx_k, dy_l>| of the grid and h the derivative scale of
+ * the edges in unit cells (max(max|dx| max|y - y_0|, max|dy| max|x - x_0|)),
+ * the edge coefficients are bounded by h^r/r!, the last row and column of the
+ * (N+1) x (N+1) tile matrix sum to E(N) = 2/N! sum_{j<=N} cmax^j h^(N-j)/j!,
+ * and the local errors add up over the cells.
+ *
+ * sigk_order_bound (host only): the least N in [1, 64] with
+ * cells * E(N) <= tol -> *N_out (and the bound); SIGK_EUNSUPPORTED with
+ * N_out = 64 if none.  SIGK_EINVAL on negative or non-finite arguments.
+ */
+int sigk_order_bound(double cmax, double h, double cells, double tol, int* N_out,
+                     double* bound_out);
+/*
+ * The same for a pair on the device: x [lx][d], y [ly][d]; the statistics
+ * (cmax over all cells, path increments and excursions) come from small
+ * kernels on `stream`, then the call WAITS for them (synchronous) and returns
+ * *order_out = the smallest compiled edge order P >= N + 1 (0 and
+ * SIGK_EUNSUPPORTED if none) and the bound at N.  ws: at least 256 bytes of
+ * device scratch.  Paths of more than 4,194,240 points are not supported.
+ */
+int sigk_estimate_order(const double* x, int64_t lx, const double* y, int64_t ly, int64_t d,
+                        double tol, int* order_out, double* bound_out, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- status */
 /* Synchronous: waits for stream, reads counters and the status word of ws. */

@@ -15,6 +15,8 @@ Functions (all FP64 in/out, numpy arrays, row-major ``[length, d]`` paths):
 * ``gram(X, Y, sym)``       Gram matrix over a thread pool (one pair per task).
 * ``ragged(pool, offsets, pairs)``  kernel values for a list of path pairs.
 * ``grad(x, y)``            continuous adjoint: (k, dk/dx, dk/dy).
+* ``pair_fixed(x, y, N)``   the fixed-order approximant k^[N] (tiles keep their
+                             (N+1) x (N+1) coefficient matrix).
 * ``cell(a, b, c, N)``      one cell's coefficient matrix and edge series.
 """
 import ctypes
@@ -61,6 +63,10 @@ def _load():
             f.restype = ctypes.c_int
             f = getattr(lib, "sigk_oracle_grad" + sfx)
             f.argtypes = [_D, ctypes.c_int64, _D, ctypes.c_int64, ctypes.c_int64, _D, _D, _D]
+            f.restype = ctypes.c_int
+            f = getattr(lib, "sigk_oracle_pair_fixed" + sfx)
+            f.argtypes = [_D, ctypes.c_int64, _D, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                          _D]
             f.restype = ctypes.c_int
             f = getattr(lib, "sigk_oracle_cell" + sfx)
             f.argtypes = [_D, ctypes.c_int, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -165,6 +171,18 @@ def grad(x, y, extended=False):
     _check(fn(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1], ctypes.byref(out),
               _ptr(gx), _ptr(gy)))
     return out.value, gx, gy
+
+
+def pair_fixed(x, y, N):
+    """k^[N](x, y): every tile keeps its (N+1) x (N+1) coefficient matrix (the
+    fixed-order approximant of the paper's error analysis)."""
+    x, y = _path(x), _path(y)
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("dimension mismatch")
+    out = ctypes.c_double()
+    _check(_load().sigk_oracle_pair_fixed_f64(_ptr(x), x.shape[0], _ptr(y), y.shape[0],
+                                              x.shape[1], int(N), ctypes.byref(out)))
+    return out.value
 
 
 def cell(a, b, c, N):

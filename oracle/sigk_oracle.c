@@ -311,6 +311,69 @@ int FN(sigk_oracle_pair)(const double* x, int64_t lx, const double* y, int64_t l
 }
 
 /*
+ * The fixed-order kernel of the paper's error analysis (App. C, first display;
+ * the same approximant as in Proposition A.3): every tile keeps the
+ * (N+1) x (N+1) coefficient matrix C~ = A o B o W with 0 <= i, j <= N and the
+ * entries of Proposition 2.8 (cell_matrix above); the next tiles' edge series
+ * are its row and column sums, kept to N+1 coefficients, with no adaptive
+ * order and no trimming.  Returns k^[N](x, y) in *k_out.
+ */
+int FN(sigk_oracle_pair_fixed)(const double* x, int64_t lx, const double* y, int64_t ly,
+                               int64_t d, int N, double* k_out)
+{
+    if (!x || !y || !k_out || d < 1 || lx < 0 || ly < 0 || N < 0 || N + 1 > NCAP)
+        return ORC_EINVAL;
+    if (lx < 2 || ly < 2) {
+        *k_out = 1.0;
+        return ORC_OK;
+    }
+    pthread_once(&ST(once), ST(init_tables));
+    const int n1 = N + 1;
+    const int64_t m = lx - 1, n = ly - 1;
+    REAL *dx = NULL, *dy = NULL;
+    REAL* bot = (REAL*)malloc((size_t)m * n1 * sizeof(REAL));
+    REAL* C = (REAL*)malloc((size_t)n1 * n1 * sizeof(REAL));
+    REAL left[NCAP], right[NCAP];
+    int rc = (bot && C) ? ORC_OK : ORC_ENOMEM;
+    if (!rc) rc = ST(increments)(x, lx, d, &dx);
+    if (!rc) rc = ST(increments)(y, ly, d, &dy);
+    if (rc) goto done;
+    for (int64_t k = 0; k < m; ++k)
+        for (int i = 0; i < n1; ++i) bot[(size_t)k * n1 + i] = i == 0 ? 1 : 0;
+    for (int64_t l = 0; l < n; ++l) {
+        for (int j = 0; j < n1; ++j) left[j] = j == 0 ? 1 : 0;
+        for (int64_t k = 0; k < m; ++k) {
+            REAL rho = 0;
+            for (int64_t ch = 0; ch < d; ++ch) rho += dx[k * d + ch] * dy[l * d + ch];
+            REAL* col = bot + (size_t)k * n1; /* bottom edge in, top edge out */
+            ST(cell_matrix)(col, n1, left, n1, rho, n1, C);
+            for (int i = 0; i < n1; ++i) {
+                REAL sum = 0;
+                for (int j = 0; j < n1; ++j) sum += C[(size_t)i * n1 + j];
+                col[i] = sum; /* top edge, kept to N+1 coefficients */
+            }
+            for (int j = 0; j < n1; ++j) {
+                REAL sum = 0;
+                for (int i = 0; i < n1; ++i) sum += C[(size_t)i * n1 + j];
+                right[j] = sum; /* right edge */
+            }
+            for (int j = 0; j < n1; ++j) left[j] = right[j];
+        }
+    }
+    {
+        REAL kt = 0;
+        for (int i = 0; i < n1; ++i) kt += bot[(size_t)(m - 1) * n1 + i];
+        *k_out = (double)kt;
+    }
+done:
+    free(dx);
+    free(dy);
+    free(bot);
+    free(C);
+    return rc;
+}
+
+/*
  * One cell in isolation (for unit tests of the cell map): inputs a (la), b (lb)
  * monomial coefficients, c; outputs the N x N matrix C (N given) and the top
  * and right edge series of length N (untrimmed).

@@ -20,8 +20,11 @@ SIGK_EUNSUPPORTED = -4
 WARN_TRUNC = 1
 WARN_NONFINITE = 2
 ERR_WATCHDOG = 4
+ERR_TABLE = 8
 
 FLAG_FIXED_DEPTH = 1
+FLAG_SQUARE = 2
+FLAG_FIELD = 4
 
 STATIC_WS_BYTES = 64 << 20  # SIGK_STATIC_WS_BYTES
 
@@ -43,7 +46,9 @@ class Opts(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_uint64), ("flops", ctypes.c_uint64),
-                ("status", ctypes.c_uint32), ("order", ctypes.c_uint32)]
+                ("status", ctypes.c_uint32), ("order", ctypes.c_uint32),
+                ("trunc_est", ctypes.c_double), ("bwd_cells", ctypes.c_uint64),
+                ("bwd_flops", ctypes.c_uint64)]
 
 
 _lib = None
@@ -76,17 +81,23 @@ SIGNATURES = {
     "sigk_plan_cells": (ctypes.c_uint64, [_P]),
     "sigk_plan_upload": (ctypes.c_int, [_P, _P, _SZ, _P]),
     "sigk_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
-    "sigk_gram_ragged": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(Opts), _P,
-                                        _P, _SZ, _P]),
-    "sigk_gram_ragged_workspace_size": (ctypes.c_int, [_P, _I64, _I64, _P, _I64,
+    "sigk_gram_ragged": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _P, _I64, _I64,
+                                        ctypes.POINTER(Opts), _P, _P, _SZ, _P]),
+    "sigk_gram_ragged_workspace_size": (ctypes.c_int, [_I64, _I64, _I64, _I64, _I64,
                                                        ctypes.POINTER(Opts), ctypes.POINTER(_SZ)]),
-    "sigk_backward_workspace_size": (ctypes.c_int, [_P, _I64, _I64, _P, _I64,
+    "sigk_backward_workspace_size": (ctypes.c_int, [_I64, _I64, _I64, _I64, _I64,
                                                     ctypes.POINTER(Opts), ctypes.POINTER(_SZ)]),
-    "sigk_backward": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, ctypes.POINTER(Opts), _P,
-                                     _P, _SZ, _P]),
+    "sigk_backward": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _P, _I64, _I64, _P,
+                                     ctypes.POINTER(Opts), _P, _P, _SZ, _P]),
     "sigk_plan_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_run_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_backward_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
+    "sigk_order_bound": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "sigk_estimate_order": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_double), _P, _SZ, _P]),
     "sigk_read_counters": (ctypes.c_int, [_P, ctypes.POINTER(Counters), _P]),
     "sigk_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), _P]),
 }
@@ -115,7 +126,8 @@ def check(rc):
         raise SigkError(rc, msg.decode() if msg else "?")
 
 
-def make_opts(order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False):
+def make_opts(order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, square=False,
+              field=False):
     o = Opts()
     load().sigk_default_opts(ctypes.byref(o))
     if order is not None:
@@ -125,5 +137,6 @@ def make_opts(order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False):
     if tail_tol is not None:
         o.tail_tol = float(tail_tol)
     o.grid = int(grid)
-    o.flags = FLAG_FIXED_DEPTH if fixed_depth else 0
+    o.flags = ((FLAG_FIXED_DEPTH if fixed_depth else 0) | (FLAG_SQUARE if square else 0) |
+               (FLAG_FIELD if field else 0))
     return o

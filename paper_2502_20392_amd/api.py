@@ -18,6 +18,7 @@ no truncation warning (this synchronises).
 """
 import ctypes
 import threading
+import warnings
 
 import numpy as np
 import torch
@@ -101,12 +102,14 @@ def last_workspace():
 
 
 def counters(ws=None):
-    """Read (cells, flops, status, order) of the last call that used ws (synchronises)."""
+    """Read cells, flops, status, order and the largest per-pair truncation
+    estimate of the last call that used ws (synchronises)."""
     ws = ws if ws is not None else last_workspace()
     c = _lib.Counters()
     _lib.check(_lib.load().sigk_read_counters(_ptr(ws), ctypes.byref(c), _stream()))
     return {"cells": int(c.cells), "flops": int(c.flops), "status": int(c.status),
-            "order": int(c.order)}
+            "order": int(c.order), "trunc_est": float(c.trunc_est),
+            "bwd_cells": int(c.bwd_cells), "bwd_flops": int(c.bwd_flops)}
 
 
 def _auto(run, order, order_hint):
@@ -127,8 +130,11 @@ def _auto(run, order, order_hint):
 
 
 def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
-         order_hint=6):
-    """k(x, y) for paths x [lx, d], y [ly, d] (FP64, on the GPU).  Returns a 0-d tensor."""
+         order_hint=6, square=False, field=False):
+    """k(x, y) for paths x [lx, d], y [ly, d] (FP64, on the GPU).  Returns a 0-d tensor.
+
+    fixed_depth=True, square=True, order=8: the paper's fixed order N = 7 (every
+    tile keeps its 8 x 8 coefficient matrix)."""
     x = _check_paths(x, "x", 2)
     y = _check_paths(y, "y", 2)
     if x.shape[1] != y.shape[1]:
@@ -136,7 +142,7 @@ def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=
     lib = _lib.load()
 
     def run(p):
-        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth)
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field)
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_pair_workspace_size(x.shape[0], y.shape[0], x.shape[1],
                                                 ctypes.byref(o), ctypes.byref(nb)))
@@ -150,7 +156,7 @@ def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=
 
 
 def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
-         order_hint=6):
+         order_hint=6, square=False, field=False):
     """Gram matrix G[i, j] = k(X_i, Y_j); X [nx, lx, d], Y [ny, ly, d].  Y=None: symmetric."""
     X = _check_paths(X, "X", 3)
     sym = Y is None
@@ -162,7 +168,7 @@ def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False
     ny, ly, _ = Y.shape
 
     def run(p):
-        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth)
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field)
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_gram_workspace_size(nx, ny, lx, ly, d, int(sym), ctypes.byref(o),
                                                 ctypes.byref(nb)))
@@ -196,6 +202,35 @@ def gram_static(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_dept
     return G
 
 
+def order_bound(cmax, h, cells, tol=1e-10):
+    """sigk_order_bound: (N, bound) of the a-priori estimate from path statistics."""
+    n = ctypes.c_int()
+    b = ctypes.c_double()
+    rc = _lib.load().sigk_order_bound(float(cmax), float(h), float(cells), float(tol),
+                                      ctypes.byref(n), ctypes.byref(b))
+    if rc not in (_lib.SIGK_OK, _lib.SIGK_EUNSUPPORTED):
+        _lib.check(rc)
+    return n.value, b.value
+
+
+def estimate_order(x, y, tol=1e-10):
+    """sigk_estimate_order: (compiled order P, bound) for the pair x, y before any
+    sweep (synchronises).  P is 0 when no compiled order meets tol."""
+    x = _check_paths(x, "x", 2)
+    y = _check_paths(y, "y", 2)
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same number of channels")
+    w = workspace(256, x.device)
+    p = ctypes.c_int()
+    b = ctypes.c_double()
+    rc = _lib.load().sigk_estimate_order(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1],
+                                         float(tol), ctypes.byref(p), ctypes.byref(b), _ptr(w),
+                                         w.numel(), _stream())
+    if rc not in (_lib.SIGK_OK, _lib.SIGK_EUNSUPPORTED):
+        _lib.check(rc)
+    return p.value, b.value
+
+
 class RaggedPlan:
     """A ragged batch of path pairs over one pool of concatenated paths.
 
@@ -205,13 +240,13 @@ class RaggedPlan:
     """
 
     def __init__(self, offsets, pairs, d, order=12, tol=None, tail_tol=None, grid=0,
-                 fixed_depth=False, device="cuda"):
+                 fixed_depth=False, device="cuda", square=False):
         lib = _lib.load()
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         self.d = int(d)
         self.npairs = self.pairs.shape[0]
-        self.opts = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+        self.opts = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth, square)
         h = ctypes.c_void_p()
         _lib.check(lib.sigk_plan_ragged(self.offsets.ctypes.data_as(ctypes.c_void_p),
                                         self.offsets.shape[0] - 1, self.d,
@@ -323,60 +358,128 @@ def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixe
     return _auto(run, order, order_hint)
 
 
-def gram_ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0,
-                fixed_depth=False):
-    """sigk_gram_ragged: k for each pair of a pool in one call (host offsets / pairs;
-    synchronous, not capturable; use RaggedPlan for repeated or captured runs)."""
-    off = np.ascontiguousarray(offsets, dtype=np.int64)
-    pool = _check_pool(pool, off, _check_paths(pool, "pool", 2).shape[1])
-    prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+def _device_tables(pool, offsets, pairs, max_len):
+    """offsets / pairs as device tensors on the pool's GPU and the max_len bound.
+
+    Host (numpy) tables are copied to the device and max_len is taken from them
+    when not given; device tables need max_len from the caller (no host read)."""
+    dev = pool.device
+    if isinstance(offsets, torch.Tensor):
+        if not offsets.is_cuda or offsets.device != dev or offsets.dtype != torch.int64:
+            raise TypeError(f"offsets must be an int64 tensor on {dev}")
+        off_d = offsets.contiguous()
+        if max_len is None:
+            raise ValueError("max_len is required with device offsets")
+    else:
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if max_len is None:
+            max_len = int(np.diff(off).max()) if off.shape[0] > 1 else 0
+        off_d = torch.from_numpy(off).to(dev)
+    if isinstance(pairs, torch.Tensor):
+        if not pairs.is_cuda or pairs.device != dev or pairs.dtype != torch.int32:
+            raise TypeError(f"pairs must be an int32 tensor on {dev}")
+        prs_d = pairs.reshape(-1, 2).contiguous()
+    else:
+        prs_d = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)).to(dev)
+    return off_d, prs_d, int(max_len)
+
+
+def gram_ragged(pool, offsets, pairs, max_len=None, order=12, tol=None, tail_tol=None, grid=0,
+                fixed_depth=False, ws=None, out=None, square=False):
+    """sigk_gram_ragged: k for each pair of a pool in one asynchronous call on
+    device tables (numpy tables are copied to the device first); capturable in
+    a HIP graph once ``ws`` and ``out`` are given and the tables are on the GPU."""
+    pool = _check_paths(pool, "pool", 2)
+    if not isinstance(offsets, torch.Tensor):
+        _check_pool(pool, np.asarray(offsets), pool.shape[1])
+    off_d, prs_d, max_len = _device_tables(pool, offsets, pairs, max_len)
     lib = _lib.load()
-    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth, square)
+    npaths, npairs = off_d.numel() - 1, prs_d.shape[0]
     nb = ctypes.c_size_t()
-    _lib.check(lib.sigk_gram_ragged_workspace_size(off.ctypes.data_as(ctypes.c_void_p),
-                                                   off.shape[0] - 1, pool.shape[1],
-                                                   prs.ctypes.data_as(ctypes.c_void_p),
-                                                   prs.shape[0], ctypes.byref(o),
+    _lib.check(lib.sigk_gram_ragged_workspace_size(npaths, npairs, max_len, pool.shape[0],
+                                                   pool.shape[1], ctypes.byref(o),
                                                    ctypes.byref(nb)))
-    w = workspace(nb.value, pool.device)
-    out = torch.empty(prs.shape[0], dtype=torch.float64, device=pool.device)
-    _lib.check(lib.sigk_gram_ragged(_ptr(pool), off.ctypes.data_as(ctypes.c_void_p),
-                                    off.shape[0] - 1, pool.shape[1],
-                                    prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
-                                    ctypes.byref(o), _ptr(out), _ptr(w), w.numel(), _stream()))
+    w = _user_ws(ws, nb.value, pool.device)
+    if out is None:
+        out = torch.empty(npairs, dtype=torch.float64, device=pool.device)
+    _check_buffer(out, "out", npairs, pool.device)
+    _lib.check(lib.sigk_gram_ragged(_ptr(pool), pool.shape[0], _ptr(off_d), npaths,
+                                    pool.shape[1], _ptr(prs_d), npairs, max_len, ctypes.byref(o),
+                                    _ptr(out), _ptr(w), w.numel(), _stream()))
     _tls.ws = w
     return out
 
 
-def backward(pool, offsets, pairs, grad_out, grad_pool=None, order=12, tol=None, tail_tol=None,
-             grid=0, fixed_depth=False):
-    """sigk_backward: grad_pool += d(sum_p grad_out[p] k_p)/d pool in one call (host
-    offsets / pairs; synchronous)."""
-    off = np.ascontiguousarray(offsets, dtype=np.int64)
-    pool = _check_pool(pool, off, _check_paths(pool, "pool", 2).shape[1])
-    prs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
-    grad_out = _grad_out(grad_out, prs.shape[0], pool.device)
+def backward(pool, offsets, pairs, grad_out, grad_pool=None, max_len=None, order=12, tol=None,
+             tail_tol=None, grid=0, fixed_depth=False, ws=None, square=False):
+    """sigk_backward: grad_pool += d(sum_p grad_out[p] k_p)/d pool in one
+    asynchronous call on device tables (numpy tables are copied first)."""
+    pool = _check_paths(pool, "pool", 2)
+    if not isinstance(offsets, torch.Tensor):
+        _check_pool(pool, np.asarray(offsets), pool.shape[1])
+    off_d, prs_d, max_len = _device_tables(pool, offsets, pairs, max_len)
+    npaths, npairs = off_d.numel() - 1, prs_d.shape[0]
+    grad_out = _grad_out(grad_out, npairs, pool.device)
     if grad_pool is None:
         grad_pool = torch.zeros_like(pool)
     _check_buffer(grad_pool, "grad_pool", pool.numel(), pool.device, exact=True)
     lib = _lib.load()
-    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth, square)
     nb = ctypes.c_size_t()
-    _lib.check(lib.sigk_backward_workspace_size(off.ctypes.data_as(ctypes.c_void_p),
-                                                off.shape[0] - 1, pool.shape[1],
-                                                prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
-                                                ctypes.byref(o), ctypes.byref(nb)))
-    w = workspace(nb.value, pool.device)
-    _lib.check(lib.sigk_backward(_ptr(pool), off.ctypes.data_as(ctypes.c_void_p),
-                                 off.shape[0] - 1, pool.shape[1],
-                                 prs.ctypes.data_as(ctypes.c_void_p), prs.shape[0],
-                                 _ptr(grad_out), ctypes.byref(o), _ptr(grad_pool), _ptr(w),
-                                 w.numel(), _stream()))
+    _lib.check(lib.sigk_backward_workspace_size(npaths, npairs, max_len, pool.shape[0],
+                                                pool.shape[1], ctypes.byref(o), ctypes.byref(nb)))
+    w = _user_ws(ws, nb.value, pool.device)
+    _lib.check(lib.sigk_backward(_ptr(pool), pool.shape[0], _ptr(off_d), npaths, pool.shape[1],
+                                 _ptr(prs_d), npairs, max_len, _ptr(grad_out), ctypes.byref(o),
+                                 _ptr(grad_pool), _ptr(w), w.numel(), _stream()))
     _tls.ws = w
     return grad_pool
 
 
 # ------------------------------------------------------------------ autograd
+
+def _check_status(st, where):
+    """Raise on a watchdog trip or a non-finite value, warn on a truncation warning."""
+    if st & _lib.ERR_WATCHDOG:
+        raise RuntimeError(f"libsigk ({where}): a dependency wait timed out; results invalid")
+    if st & _lib.WARN_NONFINITE:
+        raise FloatingPointError(f"libsigk ({where}): NaN or Inf in the kernel values")
+    if st & _lib.WARN_TRUNC:
+        warnings.warn(f"libsigk ({where}): truncation estimate above its budget; raise order",
+                      RuntimeWarning, stacklevel=3)
+
+
+class _Tally:
+    """Counters of the library calls of one autograd forward and backward."""
+
+    def __init__(self):
+        self.status = 0
+        self.cells = self.flops = self.bwd_cells = self.bwd_flops = 0
+        self.trunc_est = 0.0
+
+    def add(self, ws, backward=False):
+        c = counters(ws)
+        self.status |= c["status"]
+        if backward:
+            self.bwd_cells += c["bwd_cells"]
+            self.bwd_flops += c["bwd_flops"]
+        else:
+            self.cells += c["cells"]
+            self.flops += c["flops"]
+            self.trunc_est = max(self.trunc_est, c["trunc_est"])
+
+    def as_dict(self):
+        return dict(status=self.status, cells=self.cells, flops=self.flops,
+                    bwd_cells=self.bwd_cells, bwd_flops=self.bwd_flops, trunc_est=self.trunc_est)
+
+
+def last_autograd_counters():
+    """Counters (status, cells, flops, bwd_cells, bwd_flops, trunc_est) of the last
+    ``sigkernel_gram`` / ``mmd2`` forward (and its backward) run with check=True."""
+    t = getattr(_tls, "tally", None)
+    return t.as_dict() if t is not None else None
+
 
 def _pool_and_pairs(X, Y, symmetric):
     """Pool [X; Y] (paths back to back) and the pair table of a Gram matrix."""
@@ -400,7 +503,7 @@ class _GramFunction(torch.autograd.Function):
     """G = [k(X_i, Y_j)] with the adjoint sweep as backward."""
 
     @staticmethod
-    def forward(ctx, X, Y, order, tol, symmetric):
+    def forward(ctx, X, Y, order, tol, symmetric, check):
         pool, offsets, pairs = _pool_and_pairs(X, Y, symmetric)
         plan = RaggedPlan(offsets, pairs, X.shape[2], order=order, tol=tol, device=X.device)
         grad = X.requires_grad or (Y is not None and Y.requires_grad)
@@ -408,6 +511,11 @@ class _GramFunction(torch.autograd.Function):
         # the checkpoints the adjoint needs (no second forward in backward)
         vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
         ctx.checkpointed = grad
+        ctx.check = check
+        if check:
+            ctx.tally = _tls.tally = _Tally()
+            ctx.tally.add(plan.ws)
+            _check_status(ctx.tally.status, "Gram forward")
         nx = X.shape[0]
         ny = nx if symmetric else Y.shape[0]
         G = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
@@ -433,20 +541,27 @@ class _GramFunction(torch.autograd.Function):
         else:
             w = gG.reshape(-1)
         gpool = ctx.plan.backward(ctx.pool, w.contiguous(), checkpointed=ctx.checkpointed)
+        if ctx.check:
+            ctx.tally.add(ctx.plan.ws, backward=True)
+            _check_status(ctx.tally.status, "Gram backward")
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gX = gpool[:nxp].reshape(xs)
         gY = None if ctx.symmetric else gpool[nxp:].reshape(ys)
-        return gX, gY, None, None, None
+        return gX, gY, None, None, None, None
 
 
-def sigkernel_gram(X, Y=None, order=12, tol=None):
-    """Differentiable Gram matrix of signature kernels (FP64, GPU)."""
+def sigkernel_gram(X, Y=None, order=12, tol=None, check=False):
+    """Differentiable Gram matrix of signature kernels (FP64, GPU).
+
+    check: after the forward and the backward launches, read the device status
+    (synchronises): raise on a watchdog trip or a non-finite value, warn on a
+    truncation warning; the counters are kept for ``last_autograd_counters``."""
     X = _check_paths(X, "X", 3)
     if Y is None:
-        return _GramFunction.apply(X, None, order, tol, True)
+        return _GramFunction.apply(X, None, order, tol, True, check)
     Y = _check_paths(Y, "Y", 3)
-    return _GramFunction.apply(X, Y, order, tol, False)
+    return _GramFunction.apply(X, Y, order, tol, False, check)
 
 
 class _MMD2Function(torch.autograd.Function):
@@ -458,7 +573,7 @@ class _MMD2Function(torch.autograd.Function):
     runs in a plain forward launch."""
 
     @staticmethod
-    def forward(ctx, X, Y, order, tol):
+    def forward(ctx, X, Y, order, tol, check):
         nx, lx, d = X.shape
         ny, ly, _ = Y.shape
         pool = torch.cat([X.reshape(-1, d), Y.reshape(-1, d)], dim=0).contiguous()
@@ -476,6 +591,7 @@ class _MMD2Function(torch.autograd.Function):
         use = [need_x, need_y, need_x or need_y]  # XX, YY, XY blocks with a gradient
         total = torch.zeros((), dtype=torch.float64, device=X.device)
         plan_g = None
+        tally = _Tally() if check else None
         for grad in (True, False):
             sel = [u == grad for u in use]
             if not any(sel):
@@ -484,12 +600,18 @@ class _MMD2Function(torch.autograd.Function):
             w = np.concatenate([x for x, u in zip(weights, sel) if u])
             plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
             vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
+            if tally is not None:
+                tally.add(plan.ws)
             wt = torch.from_numpy(w).to(X.device)
             total = total + (vals * wt).sum()
             if grad:
                 plan_g, w_g = plan, wt
         ctx.plan = plan_g
         ctx.w = w_g if plan_g is not None else None
+        ctx.tally = tally
+        if tally is not None:
+            _tls.tally = tally
+            _check_status(tally.status, "MMD^2 forward")
         ctx.pool, ctx.shapes = pool, (X.shape, Y.shape)
         return total
 
@@ -497,15 +619,21 @@ class _MMD2Function(torch.autograd.Function):
     def backward(ctx, g):
         need_x, need_y = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if ctx.plan is None or not (need_x or need_y):
-            return None, None, None, None
+            return None, None, None, None, None
         gpool = ctx.plan.backward(ctx.pool, (ctx.w * g).contiguous(), checkpointed=True)
+        if ctx.tally is not None:
+            ctx.tally.add(ctx.plan.ws, backward=True)
+            _check_status(ctx.tally.status, "MMD^2 backward")
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gx = gpool[:nxp].reshape(xs) if need_x else None
         gy = gpool[nxp:].reshape(ys) if need_y else None
-        return gx, gy, None, None
+        return gx, gy, None, None, None
 
 
-def mmd2(X, Y, order=12, tol=None):
-    """Differentiable biased MMD^2 between path sets X [nx, lx, d] and Y [ny, ly, d]."""
-    return _MMD2Function.apply(_check_paths(X, "X", 3), _check_paths(Y, "Y", 3), order, tol)
+def mmd2(X, Y, order=12, tol=None, check=False):
+    """Differentiable biased MMD^2 between path sets X [nx, lx, d] and Y [ny, ly, d].
+
+    check: as for ``sigkernel_gram`` (status read after forward and backward)."""
+    return _MMD2Function.apply(_check_paths(X, "X", 3), _check_paths(Y, "Y", 3), order, tol,
+                               check)

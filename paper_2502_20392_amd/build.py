@@ -62,9 +62,15 @@ def _compile(src, obj, defs, force):
 
 def build(force: bool = False, jobs: int = 0, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    units = [("sigk_api.hip", "api.o", []), ("sigk_static.hip", "static.o", [])]
+    units = [("sigk_api.hip", "api.o", []), ("sigk_static.hip", "static.o", []),
+             ("sigk_estimate.hip", "estimate.o", []), ("sigk_delta.hip", "delta.o", [])]
     for p, d in _variants("SIGK_FWD_VARIANTS"):
         units.append(("sigk_fwd.hip", f"fwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
+    for p, d in _variants("SIGK_FWDG_VARIANTS"):
+        units.append(("sigk_fwd.hip", f"fwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
+    for p, d in _variants("SIGK_FWDSQ_VARIANTS"):
+        units.append(("sigk_fwd.hip", f"fwdsq_{p}_{d}.o",
+                      [("SIGK_P", p), ("SIGK_D", d), ("SIGK_SQ", 1)]))
     for p, d in _variants("SIGK_BWD_VARIANTS"):
         units.append(("sigk_bwd.hip", f"bwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
     jobs = jobs or min(16, os.cpu_count() or 4)

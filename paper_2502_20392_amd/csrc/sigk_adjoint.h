@@ -26,6 +26,27 @@
 
 namespace sigk {
 
+// Algorithmic flops of one cell's adjoint at edge order P, Neumann depth q,
+// d channels (FMA = 2 flops), counted on cell_adjoint_fixed:
+//   powers c^n and e_n                      3q - 1 mul
+//   Hankel sums of both edges               2q(P-2) FMA + 2q mul
+//   left edge from the right edge           q(q+1)/2 + (P-1-q)q + q FMA
+//   n = 0 rows                              2(P-1) FMA + (P-1) mul
+//   terms n = 1..q (Toeplitz transposes
+//     and dL/dc)                            sum_n (4(P-n) + 2) FMA + q mul
+//   Hankel transposes (nested)              2q(P-1) FMA + 2q + (P-1) mul
+//   B_0 := A_0, c = <dx, dy>, dL/dc chained
+//     into both increments                  1 add, 3d FMA
+__host__ __device__ constexpr long long adjoint_flops(int P, int q, int d) {
+    const long long fma_n = 2LL * q * (P - 2) + (long long)q * (q + 1) / 2 +
+                            (long long)(P - 1 - q) * q + q + 2LL * (P - 1) +
+                            4LL * q * P - 2LL * q * (q + 1) + 2LL * q + 2LL * q * (P - 1) +
+                            3LL * d;
+    const long long mul_n = q > 0 ? (3LL * q - 1) + 2LL * q + q + 2LL * q + 2LL * (P - 1)
+                                  : (long long)(P - 1);
+    return 2 * fma_n + mul_n + 1;
+}
+
 // Powers e_n = c^n/n!, n = N..q (e[0] = 1).
 template <int P, int N, class RC>
 __device__ __forceinline__ void powers(double c, int q, double (&e)[P], const RC& R) {

@@ -40,6 +40,12 @@ const Variant kFwdTable[] = {SIGK_FWD_VARIANTS(SIGK_V_FWD)};
 #define SIGK_V_BWD(P, D) {P, D, nullptr, nullptr, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_ckpt_##P##_##D, occupancy_bwd_##P##_##D},
 const Variant kBwdTable[] = {SIGK_BWD_VARIANTS(SIGK_V_BWD)};
 #undef SIGK_V_BWD
+#define SIGK_V_FWDSQ(P, D) {P, D, launch_fwdsq_##P##_##D, occupancy_fwdsq_##P##_##D, nullptr, nullptr, nullptr, nullptr},
+const Variant kFwdSqTable[] = {SIGK_FWDSQ_VARIANTS(SIGK_V_FWDSQ)};
+#undef SIGK_V_FWDSQ
+#define SIGK_V_FWDG(P, D) {P, D, launch_fwd_##P##_##D, occupancy_fwd_##P##_##D, nullptr, nullptr, nullptr, nullptr},
+const Variant kFwdGTable[] = {SIGK_FWDG_VARIANTS(SIGK_V_FWDG)};
+#undef SIGK_V_FWDG
 
 int round_order(int order) {
     if (order <= 0) order = 12;
@@ -52,13 +58,30 @@ int round_dim(int64_t d) {
         if (d <= v) return v;
     return 0;
 }
+// Channel bucket of a Gram / pair call: 0 (coefficients from the matrix-core
+// field stage) for d > 32 or on request, else the compiled bucket.
+int bucket_of(int64_t d, uint32_t flags) {
+    return (d > 32 || (flags & SIGK_FLAG_FIELD)) ? 0 : round_dim(d);
+}
 
-const Variant* find_fwd(int P, int D) {
+const Variant* find_fwd(int P, int D, uint32_t flags = 0) {
+    if (D == 0) {
+        if (flags & SIGK_FLAG_SQUARE) return nullptr;
+        for (const Variant& v : kFwdGTable)
+            if (v.P == P) return &v;
+        return nullptr;
+    }
+    if (flags & SIGK_FLAG_SQUARE) {
+        for (const Variant& v : kFwdSqTable)
+            if (v.P == P && v.D == D) return &v;
+        return nullptr;
+    }
     for (const Variant& v : kFwdTable)
         if (v.P == P && v.D == D) return &v;
     return nullptr;
 }
-const Variant* find_bwd(int P, int D) {
+const Variant* find_bwd(int P, int D, uint32_t flags = 0) {
+    if (flags & SIGK_FLAG_SQUARE) return nullptr;  // forward-only mode
     for (const Variant& v : kBwdTable)
         if (v.P == P && v.D == D) return &v;
     return nullptr;
@@ -74,7 +97,7 @@ int g_cus[64] = {0};
 
 // resident workgroups per device for a variant's forward, adjoint or
 // checkpoint kernel (their register and LDS footprints differ)
-enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2 };
+enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2, kKernelFwdSq = 3 };
 
 int device_wgs(int P, int D, int kind) {
     int dev = 0;
@@ -88,8 +111,8 @@ int device_wgs(int P, int D, int kind) {
         g_cus[dev] = cus;
     }
     int occ = 0;
-    if (kind == kKernelFwd) {
-        const Variant* v = find_fwd(P, D);
+    if (kind == kKernelFwd || kind == kKernelFwdSq) {
+        const Variant* v = find_fwd(P, D, kind == kKernelFwdSq ? SIGK_FLAG_SQUARE : 0);
         occ = v ? v->occ_fwd() : 0;
     } else {
         const Variant* v = find_bwd(P, D);
@@ -123,14 +146,19 @@ void fill_common(FwdArgs& a, const sigk_opts& o, int P, int64_t d, int64_t max_c
         tau *= 1.0 - 1e-12;  // round the bound outward
         a.tau2[n] = (o.flags & SIGK_FLAG_FIXED_DEPTH) ? -1.0 : tau * tau;
     }
-    a.tail_tol = o.tail_tol > 0 ? o.tail_tol : std::ldexp(1.0, -50);
     a.d = (int)d;
     a.watchdog_ticks = 2000000000LL;  // 20 s of the 100 MHz counter
     (void)P;
 }
 
+// Budget of a pair's estimated relative truncation error (sum of the cells'
+// local estimates, see the strip kernel): the Neumann tolerance's accumulated
+// bound, 2^-36 (about 1.5e-11).
+double default_budget() { return std::ldexp(1.0, -36); }
+double budget_of(const sigk_opts& o) { return o.tail_tol > 0 ? o.tail_tol : default_budget(); }
+
 __global__ void reset_kernel(WsHeader* h, int* prog, int64_t nprog, double* out, int64_t nout,
-                             unsigned order) {
+                             double* est, int64_t nest, unsigned order) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (i0 == 0) {
@@ -140,18 +168,58 @@ __global__ void reset_kernel(WsHeader* h, int* prog, int64_t nprog, double* out,
         h->cells = 0;
         h->flops = 0;
         h->order = order;
+        h->trunc_max = 0.0;
+        h->bwd_cells = 0;
+        h->bwd_flops = 0;
     }
     for (int64_t i = i0; i < nprog; i += stride) prog[i] = 0;
     // pairs without cells keep k = 1 (K = 1 on the axes)
     for (int64_t i = i0; i < nout; i += stride) out[i] = 1.0;
+    for (int64_t i = i0; i < nest; i += stride) est[i] = 0.0;
 }
 
 hipError_t launch_reset(WsHeader* h, int* prog, int64_t nprog, double* out, int64_t nout,
-                        unsigned order, hipStream_t s) {
-    int64_t n = std::max<int64_t>(std::max(nprog, nout), 1);
+                        double* est, int64_t nest, unsigned order, hipStream_t s) {
+    int64_t n = std::max<int64_t>(std::max(std::max(nprog, nout), nest), 1);
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, h, prog, nprog, out, nout,
-                       order);
+                       est, nest, order);
+    return hipGetLastError();
+}
+
+// After a forward sweep: compare every pair's truncation estimate with the
+// budget (SIGK_WARN_TRUNC above it, SIGK_WARN_NONFINITE if not finite) and
+// record the largest finite one.  One block.
+__global__ void finalize_kernel(WsHeader* h, const double* est, int64_t npairs, double budget) {
+    __shared__ double smax[256];
+    __shared__ unsigned sbits[256];
+    double mx = 0.0;
+    unsigned bits = 0;
+    for (int64_t p = threadIdx.x; p < npairs; p += blockDim.x) {
+        const double v = est[p];
+        if (!isfinite(v)) bits |= SIGK_WARN_NONFINITE;
+        else if (v > budget) bits |= SIGK_WARN_TRUNC;
+        if (isfinite(v)) mx = fmax(mx, v);
+    }
+    smax[threadIdx.x] = mx;
+    sbits[threadIdx.x] = bits;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            sbits[threadIdx.x] |= sbits[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        h->trunc_max = smax[0];
+        if (sbits[0]) h->status |= sbits[0];
+    }
+}
+
+hipError_t launch_finalize(WsHeader* h, const double* est, int64_t npairs, double budget,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, h, est, npairs, budget);
     return hipGetLastError();
 }
 
@@ -159,11 +227,12 @@ thread_local char g_errbuf[256];
 
 // ---------------------------------------------------------------- gram layout
 struct GramLayout {
-    size_t hdr = 0, prog = 0, front = 0, total = 0;
-    int64_t strips = 0, npairs = 0, nprog = 0;
+    size_t hdr = 0, prog = 0, est = 0, front = 0, field = 0, total = 0;
+    int64_t strips = 0, npairs = 0, nprog = 0, field_pair = 0;
 };
 
-GramLayout gram_layout(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int symmetric, int P) {
+GramLayout gram_layout(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int symmetric, int P,
+                       bool field = false) {
     GramLayout L;
     L.npairs = symmetric ? nx * (nx + 1) / 2 : nx * ny;
     const int64_t m = std::max<int64_t>(lx - 1, 0), n = std::max<int64_t>(ly - 1, 0);
@@ -171,8 +240,12 @@ GramLayout gram_layout(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int symme
     L.nprog = L.npairs * L.strips;
     L.hdr = 0;
     L.prog = align256(sizeof(WsHeader));
-    L.front = align256(L.prog + sizeof(int) * (size_t)std::max<int64_t>(L.nprog, 1));
-    L.total = align256(L.front + sizeof(double) * (size_t)(L.npairs * m * P));
+    L.est = align256(L.prog + sizeof(int) * (size_t)std::max<int64_t>(L.nprog, 1));
+    L.front = align256(L.est + sizeof(double) * (size_t)std::max<int64_t>(L.npairs, 1));
+    L.field = align256(L.front + sizeof(double) * (size_t)(L.npairs * m * P));
+    // the cell-coefficient field: per pair [strips][delta_steps(m)][64]
+    L.field_pair = field && m > 0 && n > 0 ? L.strips * delta_steps(m) * kWave : 0;
+    L.total = align256(L.field + sizeof(double) * (size_t)(L.npairs * L.field_pair));
     return L;
 }
 
@@ -192,6 +265,7 @@ struct sigk_plan {
     std::vector<PairDesc> desc;
     std::vector<Ticket> tickets;      // forward order (longest remaining chain first)
     std::vector<Ticket> tickets_rev;  // adjoint order (the same, top-down)
+    int64_t ntk = 0;                  // ticket slots (forward and adjoint tables)
     int64_t nprog = 0;
     int64_t front_doubles = 0;        // forward frontier (one row per pair)
     int64_t snap_doubles = 0;         // adjoint: per-strip frontier snapshots
@@ -202,9 +276,16 @@ struct sigk_plan {
     int64_t max_cells = 0;            // cells of the largest pair
     sigk_opts opts;
     // workspace offsets (bytes)
-    size_t o_desc = 0, o_tk = 0, o_tkr = 0, o_prog = 0, o_front = 0, fwd_total = 0;
+    size_t o_desc = 0, o_tk = 0, o_tkr = 0, o_prog = 0, o_est = 0, o_front = 0, fwd_total = 0;
     size_t o_snap = 0, o_ckpt = 0, o_lfront = 0, o_lprog = 0, o_gdx = 0, o_scr = 0,
            bwd_total = 0;
+    // tables built on the device (one-call forms): every pair is laid out at
+    // fixed strides for paths of up to max_len points; bucket counters of the
+    // forward and adjoint ticket orders
+    bool dev_tables = false;
+    int64_t max_len = 0, M = 0, S_max = 0, nbk_f = 0, nbk_b = 0;
+    int lag_f = 0, lag_b = 0;
+    size_t o_hist = 0, o_histr = 0;
 };
 
 namespace {
@@ -214,15 +295,21 @@ constexpr int kBwdMaxGrid = 2048;
 void plan_layout(sigk_plan& p) {
     size_t o = align256(sizeof(WsHeader));
     p.o_desc = o;
-    o = align256(o + sizeof(PairDesc) * std::max<size_t>(p.desc.size(), 1));
+    o = align256(o + sizeof(PairDesc) * (size_t)std::max<int64_t>(p.npairs, 1));
     p.o_tk = o;
-    o = align256(o + sizeof(Ticket) * std::max<size_t>(p.tickets.size(), 1));
+    o = align256(o + sizeof(Ticket) * (size_t)std::max<int64_t>(p.ntk, 1));
     p.o_tkr = o;
-    o = align256(o + sizeof(Ticket) * std::max<size_t>(p.tickets_rev.size(), 1));
+    o = align256(o + sizeof(Ticket) * (size_t)std::max<int64_t>(p.ntk, 1));
     p.o_prog = o;
     o = align256(o + sizeof(int) * (size_t)std::max<int64_t>(p.nprog, 1));
+    p.o_est = o;
+    o = align256(o + sizeof(double) * (size_t)std::max<int64_t>(p.npairs, 1));
     p.o_front = o;
     o = align256(o + sizeof(double) * (size_t)std::max<int64_t>(p.front_doubles, 1));
+    p.o_hist = o;
+    o = align256(o + sizeof(int) * (size_t)p.nbk_f);
+    p.o_histr = o;
+    o = align256(o + sizeof(int) * (size_t)p.nbk_b);
     p.fwd_total = o;
     // adjoint extension
     p.o_snap = o;
@@ -243,6 +330,48 @@ void plan_layout(sigk_plan& p) {
 
 bool valid_opts(const sigk_opts* o) { return o == nullptr || (std::isfinite(o->tol) && std::isfinite(o->tail_tol)); }
 
+// Reset of a plan's workspace before a forward sweep: header, progress flags,
+// truncation estimates and the outputs (k = 1 where a pair has no cells).
+hipError_t plan_reset(const sigk_plan* plan, double* out, char* base, hipStream_t s) {
+    return launch_reset((WsHeader*)base, (int*)(base + plan->o_prog), plan->nprog, out,
+                        out ? plan->npairs : 0, (double*)(base + plan->o_est), plan->npairs,
+                        (unsigned)plan->P, s);
+}
+
+// The forward sweep of a plan (after plan_reset): one persistent launch, then
+// the truncation-estimate check.
+int fwd_pass(const sigk_plan* plan, const double* pool, double* out, char* base, hipStream_t s) {
+    if (plan->ntk == 0) return SIGK_OK;
+    WsHeader* hdr = (WsHeader*)base;
+    double* est = (double*)(base + plan->o_est);
+    FwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_common(a, plan->opts, plan->P, plan->d, plan->max_cells);
+    a.mode = kModeTable;
+    a.X = pool;
+    a.Y = pool;
+    a.npairs = plan->npairs;
+    a.ntickets = plan->ntk;
+    a.desc = (const PairDesc*)(base + plan->o_desc);
+    a.tickets = (const Ticket*)(base + plan->o_tk);
+    a.out = out;
+    a.frontier = (double*)(base + plan->o_front);
+    a.progress = (int*)(base + plan->o_prog);
+    a.hdr = hdr;
+    a.trunc_est = est;
+    const Variant* v = find_fwd(plan->P, plan->D, plan->opts.flags);
+    if (!v) return SIGK_EUNSUPPORTED;
+    int grid = plan->opts.grid > 0
+                   ? plan->opts.grid
+                   : device_wgs(plan->P, plan->D,
+                                (plan->opts.flags & SIGK_FLAG_SQUARE) ? kKernelFwdSq : kKernelFwd);
+    grid = (int)std::min<int64_t>(grid, a.ntickets);
+    hipError_t e = v->fwd(a, std::max(grid, 1), s);
+    if (e == hipSuccess) e = launch_finalize(hdr, est, plan->npairs, budget_of(plan->opts), s);
+    if (e != hipSuccess) return device_error(e);
+    return SIGK_OK;
+}
+
 sigk_opts opts_or_default(const sigk_opts* o) {
     sigk_opts r;
     sigk_default_opts(&r);
@@ -258,7 +387,7 @@ void sigk_default_opts(sigk_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
     o->tol = 0.0;  // chosen by size at launch
-    o->tail_tol = std::ldexp(1.0, -50);
+    o->tail_tol = default_budget();
     o->order = 12;
 }
 
@@ -266,8 +395,8 @@ int sigk_supported_order(int order) { return round_order(order); }
 
 int sigk_device_grid(int order, int64_t d, int backward) {
     const int P = round_order(order);
-    const int D = round_dim(d);
-    if (!P || !D) return 0;
+    const int D = backward ? round_dim(d) : bucket_of(d, 0);
+    if (!P || (backward && !D) || (!backward && !find_fwd(P, D))) return 0;
     if (backward && !find_bwd(P, D)) return 0;
     return device_wgs(P, D, backward != 0 ? kKernelBwd : kKernelFwd);
 }
@@ -291,8 +420,9 @@ int sigk_gram_workspace_size(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int
     if (symmetric && (nx != ny || lx != ly)) return SIGK_EINVAL;
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
-    if (!P || !round_dim(d)) return SIGK_EUNSUPPORTED;
-    *bytes = gram_layout(nx, ny, lx, ly, symmetric, P).total;
+    const int D = bucket_of(d, op.flags);
+    if (!P || !find_fwd(P, D, op.flags)) return SIGK_EUNSUPPORTED;
+    *bytes = gram_layout(nx, ny, lx, ly, symmetric, P, D == 0).total;
     return SIGK_OK;
 }
 
@@ -306,16 +436,20 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     if (lx > INT32_MAX / 2 || ly > INT32_MAX / 2 || nx * ny > INT32_MAX) return SIGK_EINVAL;
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
-    const int D = round_dim(d);
-    if (!P || !D) return SIGK_EUNSUPPORTED;
-    const GramLayout L = gram_layout(nx, ny, lx, ly, symmetric, P);
+    const int D = bucket_of(d, op.flags);
+    const Variant* v = P ? find_fwd(P, D, op.flags) : nullptr;
+    if (!v) return SIGK_EUNSUPPORTED;
+    const GramLayout L = gram_layout(nx, ny, lx, ly, symmetric, P, D == 0);
     if (L.nprog > INT32_MAX) return SIGK_EINVAL;  // progress slots are indexed in 32 bits
+    // the field stage's grid: strips in y, pairs in z
+    if (D == 0 && (L.strips > 65535 || L.npairs > 65535)) return SIGK_EUNSUPPORTED;
     if (ws_bytes < L.total) return SIGK_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)ws;
     WsHeader* hdr = (WsHeader*)(base + L.hdr);
     int* prog = (int*)(base + L.prog);
-    hipError_t e = launch_reset(hdr, prog, L.nprog, G, nx * ny, (unsigned)P, s);
+    double* est = (double*)(base + L.est);
+    hipError_t e = launch_reset(hdr, prog, L.nprog, G, nx * ny, est, L.npairs, (unsigned)P, s);
     if (e != hipSuccess) return device_error(e);
     if (lx < 2 || ly < 2) return SIGK_OK;
     FwdArgs a;
@@ -337,11 +471,19 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     a.progress = prog;
     a.hdr = hdr;
     a.ckpt = nullptr;
-    const Variant* v = find_fwd(P, D);
-    if (!v) return SIGK_EUNSUPPORTED;
-    int grid = op.grid > 0 ? op.grid : device_wgs(P, D, kKernelFwd);
+    a.trunc_est = est;
+    if (D == 0) {
+        a.delta = (double*)(base + L.field);
+        a.delta_pair = L.field_pair;
+        e = launch_delta_gemm(a, s);
+        if (e != hipSuccess) return device_error(e);
+    }
+    int grid = op.grid > 0 ? op.grid
+                           : device_wgs(P, D, (op.flags & SIGK_FLAG_SQUARE) ? kKernelFwdSq
+                                                                          : kKernelFwd);
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->fwd(a, std::max(grid, 1), s);
+    if (e == hipSuccess) e = launch_finalize(hdr, est, L.npairs, budget_of(op), s);
     if (e != hipSuccess) return device_error(e);
     return SIGK_OK;
 }
@@ -461,6 +603,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     };
     pl->tickets = chain_order(false);
     pl->tickets_rev = chain_order(true);
+    pl->ntk = (int64_t)pl->tickets.size();
     plan_layout(*pl);
     *plan = pl;
     return SIGK_OK;
@@ -470,7 +613,11 @@ namespace {
 
 // Adjoint ticket counter (the adjoint may run long after the checkpoint pass
 // that reset the header).
-__global__ void zero_tickets_kernel(WsHeader* h) { h->ticket2 = 0; }
+__global__ void zero_tickets_kernel(WsHeader* h) {
+    h->ticket2 = 0;
+    h->bwd_cells = 0;
+    h->bwd_flops = 0;
+}
 
 __global__ void zero_kernel(int* ip, int64_t ni, double* dp, int64_t nd) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,94 +676,9 @@ int sigk_plan_run(const sigk_plan* plan, const double* pool, double* out, void* 
     if (ws_bytes < plan->fwd_total) return SIGK_EWORKSPACE;
     if (plan->npairs == 0) return SIGK_OK;
     hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
-    WsHeader* hdr = (WsHeader*)base;
-    int* prog = (int*)(base + plan->o_prog);
-    hipError_t e = launch_reset(hdr, prog, plan->nprog, out, plan->npairs, (unsigned)plan->P, s);
+    hipError_t e = plan_reset(plan, out, (char*)ws, s);
     if (e != hipSuccess) return device_error(e);
-    if (plan->tickets.empty()) return SIGK_OK;
-    FwdArgs a;
-    std::memset(&a, 0, sizeof a);
-    fill_common(a, plan->opts, plan->P, plan->d, plan->max_cells);
-    a.mode = kModeTable;
-    a.X = pool;
-    a.Y = pool;
-    a.npairs = plan->npairs;
-    a.ntickets = (int64_t)plan->tickets.size();
-    a.desc = (const PairDesc*)(base + plan->o_desc);
-    a.tickets = (const Ticket*)(base + plan->o_tk);
-    a.out = out;
-    a.frontier = (double*)(base + plan->o_front);
-    a.progress = prog;
-    a.hdr = hdr;
-    const Variant* v = find_fwd(plan->P, plan->D);
-    if (!v) return SIGK_EUNSUPPORTED;
-    int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, kKernelFwd);
-    grid = (int)std::min<int64_t>(grid, a.ntickets);
-    e = v->fwd(a, std::max(grid, 1), s);
-    if (e != hipSuccess) return device_error(e);
-    return SIGK_OK;
-}
-
-int sigk_gram_ragged_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
-                                    const int32_t* pairs, int64_t npairs, const sigk_opts* o,
-                                    size_t* bytes) {
-    if (!bytes) return SIGK_EINVAL;
-    sigk_plan* pl = nullptr;
-    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
-    if (rc) return rc;
-    *bytes = pl->fwd_total;
-    sigk_plan_destroy(pl);
-    return SIGK_OK;
-}
-
-int sigk_gram_ragged(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
-                     const int32_t* pairs, int64_t npairs, const sigk_opts* o, double* out,
-                     void* ws, size_t ws_bytes, void* stream) {
-    sigk_plan* pl = nullptr;
-    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
-    if (rc) return rc;
-    if (ws_bytes < pl->fwd_total) {
-        sigk_plan_destroy(pl);
-        return SIGK_EWORKSPACE;
-    }
-    rc = sigk_plan_upload(pl, ws, ws_bytes, stream);
-    if (!rc) rc = sigk_plan_run(pl, pool, out, ws, ws_bytes, stream);
-    // the table copies come from pageable plan memory: wait before freeing it
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (!rc && e != hipSuccess) rc = device_error(e);
-    sigk_plan_destroy(pl);
-    return rc;
-}
-
-int sigk_backward_workspace_size(const int64_t* offsets, int64_t npaths, int64_t d,
-                                 const int32_t* pairs, int64_t npairs, const sigk_opts* o,
-                                 size_t* bytes) {
-    if (!bytes) return SIGK_EINVAL;
-    sigk_plan* pl = nullptr;
-    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
-    if (rc) return rc;
-    *bytes = pl->bwd_total;
-    sigk_plan_destroy(pl);
-    return SIGK_OK;
-}
-
-int sigk_backward(const double* pool, const int64_t* offsets, int64_t npaths, int64_t d,
-                  const int32_t* pairs, int64_t npairs, const double* grad_out, const sigk_opts* o,
-                  double* grad_pool, void* ws, size_t ws_bytes, void* stream) {
-    sigk_plan* pl = nullptr;
-    int rc = sigk_plan_ragged(offsets, npaths, d, pairs, npairs, o, &pl);
-    if (rc) return rc;
-    if (ws_bytes < pl->bwd_total) {
-        sigk_plan_destroy(pl);
-        return SIGK_EWORKSPACE;
-    }
-    rc = sigk_plan_upload(pl, ws, ws_bytes, stream);
-    if (!rc) rc = sigk_plan_backward(pl, pool, grad_out, grad_pool, ws, ws_bytes, stream);
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (!rc && e != hipSuccess) rc = device_error(e);
-    sigk_plan_destroy(pl);
-    return rc;
+    return fwd_pass(plan, pool, out, (char*)ws, s);
 }
 
 // ------------------------------------------------------------------ status
@@ -630,6 +692,9 @@ int sigk_read_counters(const void* ws, sigk_counters* out, void* stream) {
     out->flops = h.flops;
     out->status = h.status;
     out->order = h.order;
+    out->trunc_est = h.trunc_max;
+    out->bwd_cells = h.bwd_cells;
+    out->bwd_flops = h.bwd_flops;
     return SIGK_OK;
 }
 
@@ -649,11 +714,11 @@ namespace {
 // the frontier row each strip reads, the wave state every kCkptEvery steps and
 // the depth of every chunk; writes the kernel values to out when out != null.
 int checkpoint_pass(const sigk_plan* plan, const Variant* v, const double* pool, double* out,
-                    char* base, hipStream_t s) {
+                    char* base, hipStream_t s, bool reset = true) {
     WsHeader* hdr = (WsHeader*)base;
     int* prog = (int*)(base + plan->o_prog);
-    hipError_t e = launch_reset(hdr, prog, plan->nprog, out, out ? plan->npairs : 0,
-                                (unsigned)plan->P, s);
+    double* est = (double*)(base + plan->o_est);
+    hipError_t e = reset ? plan_reset(plan, out, base, s) : hipSuccess;
     if (e != hipSuccess) return device_error(e);
     FwdArgs a;
     std::memset(&a, 0, sizeof a);
@@ -662,7 +727,7 @@ int checkpoint_pass(const sigk_plan* plan, const Variant* v, const double* pool,
     a.X = pool;
     a.Y = pool;
     a.npairs = plan->npairs;
-    a.ntickets = (int64_t)plan->tickets.size();
+    a.ntickets = plan->ntk;
     a.desc = (const PairDesc*)(base + plan->o_desc);
     a.tickets = (const Ticket*)(base + plan->o_tk);
     a.out = out;
@@ -670,9 +735,11 @@ int checkpoint_pass(const sigk_plan* plan, const Variant* v, const double* pool,
     a.progress = prog;
     a.hdr = hdr;
     a.ckpt = (double*)(base + plan->o_ckpt);
+    a.trunc_est = est;
     int grid = plan->opts.grid > 0 ? plan->opts.grid : device_wgs(plan->P, plan->D, kKernelCkpt);
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->ckpt(a, std::max(grid, 1), s);
+    if (e == hipSuccess) e = launch_finalize(hdr, est, plan->npairs, budget_of(plan->opts), s);
     if (e != hipSuccess) return device_error(e);
     return SIGK_OK;
 }
@@ -700,7 +767,7 @@ int adjoint_pass(const sigk_plan* plan, const Variant* v, const double* pool,
     b.f.desc = (const PairDesc*)(base + plan->o_desc);
     b.f.hdr = hdr;
     b.tickets = (const Ticket*)(base + plan->o_tkr);
-    b.ntickets = (int64_t)plan->tickets_rev.size();
+    b.ntickets = plan->ntk;
     b.grad_out = grad_out;
     b.snap = (double*)(base + plan->o_snap);
     b.ckpt = (double*)(base + plan->o_ckpt);
@@ -728,12 +795,13 @@ int sigk_plan_run_checkpointed(const sigk_plan* plan, const double* pool, double
     if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
     if (plan->npairs == 0) return SIGK_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (plan->tickets.empty()) {
+    if (plan->ntk == 0) {
         hipError_t e = launch_reset((WsHeader*)ws, (int*)((char*)ws + plan->o_prog), plan->nprog,
-                                    out, plan->npairs, (unsigned)plan->P, s);
+                                    out, plan->npairs, (double*)((char*)ws + plan->o_est),
+                                    plan->npairs, (unsigned)plan->P, s);
         return e == hipSuccess ? SIGK_OK : device_error(e);
     }
-    const Variant* v = find_bwd(plan->P, plan->D);
+    const Variant* v = find_bwd(plan->P, plan->D, plan->opts.flags);
     if (!v) return SIGK_EUNSUPPORTED;
     return checkpoint_pass(plan, v, pool, out, (char*)ws, s);
 }
@@ -744,8 +812,8 @@ int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
     if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
         return SIGK_EINVAL;
     if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
-    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
-    const Variant* v = find_bwd(plan->P, plan->D);
+    if (plan->npairs == 0 || plan->ntk == 0) return SIGK_OK;
+    const Variant* v = find_bwd(plan->P, plan->D, plan->opts.flags);
     if (!v) return SIGK_EUNSUPPORTED;
     return adjoint_pass(plan, v, pool, grad_out, grad_pool, (char*)ws, (hipStream_t)stream);
 }
@@ -755,13 +823,287 @@ int sigk_plan_backward(const sigk_plan* plan, const double* pool, const double* 
     if (!plan || !ws || (plan->npairs > 0 && (!pool || !grad_out || !grad_pool)))
         return SIGK_EINVAL;
     if (ws_bytes < plan->bwd_total) return SIGK_EWORKSPACE;
-    if (plan->npairs == 0 || plan->tickets.empty()) return SIGK_OK;
-    const Variant* v = find_bwd(plan->P, plan->D);
+    if (plan->npairs == 0 || plan->ntk == 0) return SIGK_OK;
+    const Variant* v = find_bwd(plan->P, plan->D, plan->opts.flags);
     if (!v) return SIGK_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     int rc = checkpoint_pass(plan, v, pool, nullptr, (char*)ws, s);
     if (rc) return rc;
     return adjoint_pass(plan, v, pool, grad_out, grad_pool, (char*)ws, s);
+}
+
+}  // extern "C"
+
+// ===================================================================== device tables
+//
+// One-call ragged batches (sigk_gram_ragged, sigk_backward) whose offsets and
+// pair table are device arrays: the tables the kernels need are built on the
+// device by a few small kernels, so the calls are asynchronous and can be
+// captured in a HIP graph.  Every pair is laid out at fixed strides for paths
+// of up to max_len points.  Tickets are ordered by a counting sort on the
+// strip's remaining chain (its own sweep plus one start lag per strip still to
+// follow it in its pair), in buckets one lag wide: a producer's chain is one
+// lag longer than its consumer's, so it always lands in an earlier bucket and
+// takes a smaller ticket (no wave ever waits on a ticket not yet claimed).
+namespace {
+
+__global__ void dt_desc_kernel(const int64_t* offsets, int64_t npaths, const int32_t* pairs,
+                               int64_t npairs, int64_t max_len, int64_t pool_points, int64_t d,
+                               int64_t front_stride, int64_t snap_stride, int64_t ckpt_stride,
+                               int64_t S_max, PairDesc* desc, double* out, WsHeader* h) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = i0; p < npairs; p += stride) {
+        const int32_t px = pairs[2 * p], py = pairs[2 * p + 1];
+        bool ok = px >= 0 && px < npaths && py >= 0 && py < npaths;
+        int64_t x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+        if (ok) {
+            x0 = offsets[px];
+            x1 = offsets[px + 1];
+            y0 = offsets[py];
+            y1 = offsets[py + 1];
+            ok = x0 >= 0 && x0 <= x1 && x1 - x0 <= max_len && x1 <= pool_points && y0 >= 0 &&
+                 y0 <= y1 && y1 - y0 <= max_len && y1 <= pool_points;
+        }
+        PairDesc q;
+        q.x_off = ok ? x0 * d : 0;
+        q.y_off = ok ? y0 * d : 0;
+        q.lx = ok ? (int32_t)(x1 - x0) : 0;
+        q.ly = ok ? (int32_t)(y1 - y0) : 0;
+        q.front_off = p * front_stride;
+        q.snap_off = p * snap_stride;
+        q.ckpt_off = p * ckpt_stride;
+        q.prog_off = (int32_t)(p * S_max);
+        q.out_idx = (int32_t)p;
+        q.out_idx2 = -1;
+        q.pad = 0;
+        desc[p] = q;
+        if (!ok) {
+            if (out) out[p] = __builtin_nan("");
+            atomicOr(&h->status, SIGK_ERR_TABLE);
+        }
+    }
+}
+
+__global__ void dt_clear_kernel(Ticket* tk, Ticket* tkr, int64_t nt, int* hist, int64_t nh,
+                                int* histr, int64_t nhr) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < nt; i += stride) {
+        tk[i] = Ticket{-1, -1};
+        if (tkr) tkr[i] = Ticket{-1, -1};
+    }
+    for (int64_t i = i0; i < nh; i += stride) hist[i] = 0;
+    for (int64_t i = i0; i < nhr; i += stride) histr[i] = 0;
+}
+
+// Bucket (ascending = issued first) of strip s of a pair with m columns and S
+// strips: forward chains run upwards (strips s+1.. follow), adjoint chains
+// downwards (strips ..s-1 follow).
+__device__ __forceinline__ int64_t dt_bucket(int64_t m, int64_t S, int64_t s, int lag,
+                                             int64_t nbk, bool adjoint) {
+    const int64_t after = adjoint ? s : S - 1 - s;
+    return nbk - 1 - (after * lag + m + kWave - 1) / lag;
+}
+
+// Counting sort of the tickets: count (scatter == false) or place.
+__global__ void dt_tickets_kernel(const PairDesc* desc, int64_t S_max, int64_t nt, int lag_f,
+                                  int64_t nbf, int* hist, Ticket* tk, int lag_b, int64_t nbb,
+                                  int* histr, Ticket* tkr, int scatter) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = i0; t < nt; t += stride) {
+        const int64_t p = t / S_max, s = t % S_max;
+        const PairDesc q = desc[p];
+        const int64_t m = q.lx > 1 ? q.lx - 1 : 0, n = q.ly > 1 ? q.ly - 1 : 0;
+        const int64_t S = (m > 0 && n > 0) ? (n + kWave - 1) / kWave : 0;
+        if (s >= S) continue;
+        const int64_t bf = dt_bucket(m, S, s, lag_f, nbf, false);
+        if (!scatter) {
+            atomicAdd(&hist[bf], 1);
+        } else {
+            const int slot = atomicAdd(&hist[bf], 1);
+            tk[slot] = Ticket{(int32_t)p, (int32_t)s};
+        }
+        if (histr) {
+            const int64_t bb = dt_bucket(m, S, s, lag_b, nbb, true);
+            if (!scatter) {
+                atomicAdd(&histr[bb], 1);
+            } else {
+                const int slot = atomicAdd(&histr[bb], 1);
+                tkr[slot] = Ticket{(int32_t)p, (int32_t)s};
+            }
+        }
+    }
+}
+
+// Exclusive prefix sum in place, one block of 1024 threads (bucket counts
+// -> first ticket of each bucket); histr may be null.
+__global__ void dt_scan_kernel(int* hist, int64_t nh, int* histr, int64_t nhr) {
+    __shared__ int sv[1024];
+    __shared__ int carry;
+    for (int which = 0; which < 2; ++which) {
+        int* a = which ? histr : hist;
+        const int64_t n = which ? nhr : nh;
+        if (!a) continue;
+        if (threadIdx.x == 0) carry = 0;
+        __syncthreads();
+        for (int64_t base = 0; base < n; base += 1024) {
+            const int64_t i = base + threadIdx.x;
+            const int v = i < n ? a[i] : 0;
+            sv[threadIdx.x] = v;
+            __syncthreads();
+            for (int o = 1; o < 1024; o <<= 1) {
+                const int w = (int)threadIdx.x >= o ? sv[threadIdx.x - o] : 0;
+                __syncthreads();
+                sv[threadIdx.x] += w;
+                __syncthreads();
+            }
+            if (i < n) a[i] = carry + sv[threadIdx.x] - v;
+            __syncthreads();
+            if (threadIdx.x == 1023) carry += sv[1023];
+            __syncthreads();
+        }
+    }
+}
+
+// Layout of a one-call batch (host only): bounds from the scalar arguments.
+int dev_plan(int64_t npaths, int64_t npairs, int64_t max_len, int64_t pool_points, int64_t d,
+             const sigk_opts* o, bool backward, sigk_plan& pl) {
+    if (npaths < 0 || npairs < 0 || max_len < 0 || pool_points < 0 || d < 1 || !valid_opts(o))
+        return SIGK_EINVAL;
+    if (max_len > INT32_MAX / 2 || npairs > INT32_MAX / 2) return SIGK_EINVAL;
+    const sigk_opts op = opts_or_default(o);
+    const int P = round_order(op.order);
+    const int D = round_dim(d);
+    if (!P || !D) return SIGK_EUNSUPPORTED;
+    if (backward && !find_bwd(P, D, op.flags)) return SIGK_EUNSUPPORTED;
+    pl.P = P;
+    pl.D = D;
+    pl.d = d;
+    pl.npaths = npaths;
+    pl.npairs = npairs;
+    pl.opts = op;
+    pl.pool_points = pool_points;
+    pl.dev_tables = true;
+    pl.max_len = max_len;
+    pl.M = std::max<int64_t>(max_len - 1, 0);
+    pl.S_max = (pl.M + kWave - 1) / kWave;
+    pl.ntk = npairs * pl.S_max;
+    if (pl.ntk > INT32_MAX) return SIGK_EINVAL;  // tickets and progress slots are 32-bit
+    pl.nprog = pl.ntk;
+    pl.max_cells = pl.M * pl.M;  // the default Neumann tolerance, for the largest pair
+    pl.front_doubles = npairs * pl.M * P;
+    pl.snap_doubles = backward ? pl.ntk * pl.M * P : 0;
+    pl.ckpt_doubles = backward ? pl.ntk * ckpt_strip_doubles(pl.M, P) : 0;
+    pl.lag_f = fwd_chunk_cols(P, D) + kWave - 1;
+    pl.lag_b = chunk_cols(P) + kWave - 1;
+    const int64_t chain_max = std::max<int64_t>(pl.S_max - 1, 0) * std::max(pl.lag_f, pl.lag_b) +
+                              pl.M + kWave - 1;
+    pl.nbk_f = chain_max / pl.lag_f + 1;
+    pl.nbk_b = backward ? chain_max / pl.lag_b + 1 : 0;
+    plan_layout(pl);
+    if (!backward) pl.bwd_total = pl.fwd_total;
+    return SIGK_OK;
+}
+
+int blocks_of(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+}
+
+// Reset, then the device tables (descriptors, ticket orders) of a one-call
+// batch.  out: kernel values (NaN for invalid pairs) or null.
+int dev_tables(const sigk_plan& pl, const int64_t* offsets, const int32_t* pairs, double* out,
+               char* base, bool backward, hipStream_t s) {
+    hipError_t e = plan_reset(&pl, out, base, s);
+    if (e != hipSuccess) return device_error(e);
+    PairDesc* desc = (PairDesc*)(base + pl.o_desc);
+    Ticket* tk = (Ticket*)(base + pl.o_tk);
+    Ticket* tkr = backward ? (Ticket*)(base + pl.o_tkr) : nullptr;
+    int* hist = (int*)(base + pl.o_hist);
+    int* histr = backward ? (int*)(base + pl.o_histr) : nullptr;
+    const int64_t ckpt_stride = pl.S_max * ckpt_strip_doubles(pl.M, pl.P);
+    hipLaunchKernelGGL(dt_desc_kernel, dim3(blocks_of(pl.npairs)), dim3(256), 0, s, offsets,
+                       pl.npaths, pairs, pl.npairs, pl.max_len, pl.pool_points, pl.d,
+                       pl.M * pl.P, pl.S_max * pl.M * pl.P, ckpt_stride, pl.S_max, desc, out,
+                       (WsHeader*)base);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    const int64_t nclear = std::max(pl.ntk, std::max(pl.nbk_f, pl.nbk_b));
+    hipLaunchKernelGGL(dt_clear_kernel, dim3(blocks_of(nclear)), dim3(256), 0, s, tk, tkr, pl.ntk,
+                       hist, pl.nbk_f, histr, pl.nbk_b);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    for (int scatter = 0; scatter < 2; ++scatter) {
+        hipLaunchKernelGGL(dt_tickets_kernel, dim3(blocks_of(pl.ntk)), dim3(256), 0, s, desc,
+                           pl.S_max, pl.ntk, pl.lag_f, pl.nbk_f, hist, tk, pl.lag_b, pl.nbk_b,
+                           histr, tkr, scatter);
+        if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+        if (!scatter) {
+            hipLaunchKernelGGL(dt_scan_kernel, dim3(1), dim3(1024), 0, s, hist, pl.nbk_f, histr,
+                               pl.nbk_b);
+            if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+        }
+    }
+    return SIGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sigk_gram_ragged_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,
+                                    int64_t pool_points, int64_t d, const sigk_opts* o,
+                                    size_t* bytes) {
+    if (!bytes) return SIGK_EINVAL;
+    sigk_plan pl;
+    const int rc = dev_plan(npaths, npairs, max_len, pool_points, d, o, false, pl);
+    if (rc) return rc;
+    *bytes = pl.fwd_total;
+    return SIGK_OK;
+}
+
+int sigk_gram_ragged(const double* pool, int64_t pool_points, const int64_t* offsets,
+                     int64_t npaths, int64_t d, const int32_t* pairs, int64_t npairs,
+                     int64_t max_len, const sigk_opts* o, double* out, void* ws, size_t ws_bytes,
+                     void* stream) {
+    sigk_plan pl;
+    int rc = dev_plan(npaths, npairs, max_len, pool_points, d, o, false, pl);
+    if (rc) return rc;
+    if (npairs == 0) return SIGK_OK;
+    if (!pool || !offsets || !pairs || !out || !ws) return SIGK_EINVAL;
+    if (ws_bytes < pl.fwd_total) return SIGK_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    rc = dev_tables(pl, offsets, pairs, out, (char*)ws, false, s);
+    if (rc) return rc;
+    return fwd_pass(&pl, pool, out, (char*)ws, s);
+}
+
+int sigk_backward_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,
+                                 int64_t pool_points, int64_t d, const sigk_opts* o,
+                                 size_t* bytes) {
+    if (!bytes) return SIGK_EINVAL;
+    sigk_plan pl;
+    const int rc = dev_plan(npaths, npairs, max_len, pool_points, d, o, true, pl);
+    if (rc) return rc;
+    *bytes = pl.bwd_total;
+    return SIGK_OK;
+}
+
+int sigk_backward(const double* pool, int64_t pool_points, const int64_t* offsets,
+                  int64_t npaths, int64_t d, const int32_t* pairs, int64_t npairs,
+                  int64_t max_len, const double* grad_out, const sigk_opts* o, double* grad_pool,
+                  void* ws, size_t ws_bytes, void* stream) {
+    sigk_plan pl;
+    int rc = dev_plan(npaths, npairs, max_len, pool_points, d, o, true, pl);
+    if (rc) return rc;
+    if (npairs == 0) return SIGK_OK;
+    if (!pool || !offsets || !pairs || !grad_out || !grad_pool || !ws) return SIGK_EINVAL;
+    if (ws_bytes < pl.bwd_total) return SIGK_EWORKSPACE;
+    const Variant* v = find_bwd(pl.P, pl.D);
+    hipStream_t s = (hipStream_t)stream;
+    rc = dev_tables(pl, offsets, pairs, nullptr, (char*)ws, true, s);
+    if (!rc) rc = checkpoint_pass(&pl, v, pool, nullptr, (char*)ws, s, false);
+    if (!rc) rc = adjoint_pass(&pl, v, pool, grad_out, grad_pool, (char*)ws, s);
+    return rc;
 }
 
 }  // extern "C"

@@ -47,9 +47,11 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
         if ((int64_t)t >= a.ntickets) break;
         if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
         const int pair = a.tickets[t].pair, strip = a.tickets[t].strip;
+        if (pair < 0) break;  // unused slots close a table built on the device
         Geo g = resolve(a, pair, P, 0);
         const PairDesc& pd = a.desc[pair];
         StripCtx<P, D, CH, RB> S(a, g, L, acc, strip);
+        S.pair = pair;
         const int64_t row = (int64_t)g.m * P;
         S.Fin = snap + pd.snap_off + (int64_t)strip * row;
         S.Fout = snap + pd.snap_off + (int64_t)(strip + 1) * row;
@@ -102,6 +104,8 @@ struct StripBwd {
     Recip<P, false> R;  // scalar or rematerialised constants: registers are scarce here
     int dx_lo, lin_lo, bin_chunk;
     double* scratch;
+    unsigned long long* cells;  // per-workgroup tallies (cells, algorithmic flops)
+    unsigned long long* flops;
     const double* ck;
     const double* ckq;
     const double* snap_in;   // primal frontier row read by lane 0 ([m][P])
@@ -266,9 +270,17 @@ struct StripBwd {
         }
         // adjoint over the segment, last step first; B walks back from the
         // right edge after the segment to each cell's left edge
+        const unsigned long long fl =
+            (unsigned long long)(adjoint_flops(P, Q >= 0 ? Q : q, a.d) +
+                                 cell_flops(P, Q >= 0 ? Q : q, a.d));
         for (int t = t1 - 1; t >= t0; --t) {
             const int col = t - lane;
             const bool act = lane_ok && col >= 0 && col < m;
+            {
+                const unsigned cnt = (unsigned)__builtin_popcountll(ballot(act));
+                *cells += cnt;
+                *flops += cnt * fl;
+            }
             const double* src = scratch + (int64_t)(t - t0) * (P * kWave);
             double A[P];
 #pragma unroll
@@ -402,6 +414,7 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
     const FwdArgs& a = b.f;
     const int lane = lane_id();
     double* scratch = b.scratch + (int64_t)blockIdx.x * (kCkptEvery * P * kWave);
+    unsigned long long cells = 0, flops = 0;
     for (;;) {
         unsigned t = 0;
         if (lane == 0) t = atomicAdd(&a.hdr->ticket2, 1u);
@@ -409,11 +422,14 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
         if ((int64_t)t >= b.ntickets) break;
         if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
         const int pair = b.tickets[t].pair, strip = b.tickets[t].strip;
+        if (pair < 0) break;  // unused slots close a table built on the device
         Geo g = resolve(a, pair, P, 0);
         const PairDesc& pd = a.desc[pair];
         StripBwd<P, D> S(b, g, L, strip);
         S.pd = &pd;
         S.scratch = scratch;
+        S.cells = &cells;
+        S.flops = &flops;
         S.ck = b.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
         S.ckq = S.ck + ckpt_states(g.m) * 2 * P * kWave;
         S.snap_in = b.snap + pd.snap_off + (int64_t)strip * g.m * P;
@@ -421,6 +437,10 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
         S.lam_prog = b.lam_prog + pd.prog_off;
         S.seed_scale = b.grad_out[pair];
         if (!S.sweep()) break;
+    }
+    if (lane == 0) {
+        atomicAdd(&a.hdr->bwd_cells, cells);
+        atomicAdd(&a.hdr->bwd_flops, flops);
     }
 }
 

@@ -120,6 +120,7 @@ struct Geo {
     int m, n;         // cells: columns, rows
     int64_t front;    // frontier offset (doubles)
     int64_t ckpt;     // checkpoint offset (doubles)
+    int64_t delta;    // cell-coefficient field offset (doubles; channel bucket 0)
     int prog;         // progress offset
     int o1, o2;       // output slots
 };
@@ -154,6 +155,7 @@ __device__ Geo resolve(const FwdArgs& a, int pair, int P, int64_t ckpt_per_pair)
         g.n = (int)a.ly - 1;
         g.front = (int64_t)pair * (int64_t)g.m * P * (a.ckpt ? a.strips : 1);
         g.ckpt = (int64_t)pair * ckpt_per_pair;
+        g.delta = (int64_t)pair * a.delta_pair;
         g.prog = pair * a.strips;
         g.o1 = (int)(i * a.ny + j);
         g.o2 = (a.symmetric && i != j) ? (int)(j * a.ny + i) : -1;
@@ -165,6 +167,7 @@ __device__ Geo resolve(const FwdArgs& a, int pair, int P, int64_t ckpt_per_pair)
         g.n = p.ly - 1;
         g.front = p.front_off;
         g.ckpt = p.ckpt_off;
+        g.delta = 0;
         g.prog = p.prog_off;
         g.o1 = p.out_idx;
         g.o2 = p.out_idx2;

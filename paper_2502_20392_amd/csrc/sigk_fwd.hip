@@ -7,7 +7,10 @@
 // for any grid size).  Gram mode interleaves pairs strip-major (all pairs'
 // strip 0, then strip 1, ...); table mode takes the host-built order.
 //
-// Compiled once per (P, D) variant: -DSIGK_P=<order> -DSIGK_D=<channel bucket>.
+// Compiled once per (P, D) variant: -DSIGK_P=<order> -DSIGK_D=<channel bucket>;
+// -DSIGK_SQ=1 builds the square-truncation variant (the paper's fixed-order
+// tile matrix, selected by SIGK_FLAG_SQUARE) under the launcher names
+// launch_fwdsq_P_D / occupancy_fwdsq_P_D.
 #include "sigk_strip.h"
 
 #ifndef SIGK_P
@@ -16,10 +19,13 @@
 #ifndef SIGK_D
 #define SIGK_D 8
 #endif
+#ifndef SIGK_SQ
+#define SIGK_SQ 0
+#endif
 
 namespace sigk {
 
-template <int P, int D>
+template <int P, int D, bool SQ>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 6 && D <= 8 ? 3 : 1))) fwd_kernel(FwdArgs a) {
     constexpr int CH = fwd_chunk_cols(P, D), RB = fwd_ring_cols(P, D);
     __shared__ LdsStrip<P, D, CH, RB> L;
@@ -38,9 +44,11 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <=
         } else {
             pair = a.tickets[t].pair;
             strip = a.tickets[t].strip;
+            if (pair < 0) break;  // unused slots close a table built on the device
         }
         Geo g = resolve(a, pair, P, 0);
-        StripCtx<P, D, CH, RB> S(a, g, L, acc, strip);
+        StripCtx<P, D, CH, RB, SQ> S(a, g, L, acc, strip);
+        S.pair = pair;
         S.Fout = a.frontier + g.front;
         S.Fin = S.Fout;
         S.prog = a.progress + g.prog;
@@ -59,15 +67,24 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <=
 #define SIGK_CAT3(a, b, c) a##b##_##c
 #define SIGK_NAME(pre, P, D) SIGK_CAT3(pre, P, D)
 
-hipError_t SIGK_NAME(launch_fwd_, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((fwd_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, a);
+#if SIGK_SQ
+#define SIGK_LAUNCH launch_fwdsq_
+#define SIGK_OCC occupancy_fwdsq_
+#else
+#define SIGK_LAUNCH launch_fwd_
+#define SIGK_OCC occupancy_fwd_
+#endif
+
+hipError_t SIGK_NAME(SIGK_LAUNCH, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0>), dim3(grid), dim3(kWave), 0, s,
+                       a);
     return hipGetLastError();
 }
 
-int SIGK_NAME(occupancy_fwd_, SIGK_P, SIGK_D)() {
+int SIGK_NAME(SIGK_OCC, SIGK_P, SIGK_D)() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<SIGK_P, SIGK_D>, kWave, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0>,
+                                                     kWave, 0) != hipSuccess)
         return 0;
     return nb;
 }

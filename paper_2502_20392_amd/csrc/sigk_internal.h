@@ -16,6 +16,21 @@ constexpr int kMaxP = 24;   // largest compiled edge order
     X(4, 16) X(5, 16) X(6, 16) X(8, 16) X(10, 16) X(12, 16) X(16, 16) X(20, 16) X(24, 16) \
     X(4, 32) X(5, 32) X(6, 32) X(8, 32) X(10, 32) X(12, 32) X(16, 32) X(20, 32) X(24, 32)
 
+// Forward variants that read the cell coefficients from a field computed
+// beforehand on the matrix cores (channel bucket 0: any d, used for d > 32).
+#define SIGK_FWDG_VARIANTS(X) \
+    X(4, 0) X(5, 0) X(6, 0) X(8, 0) X(10, 0) X(12, 0) X(16, 0) X(20, 0) X(24, 0)
+
+// Steps per strip stored in a cell-coefficient field (a multiple of the
+// chunk width of the channel-bucket-0 sweep).
+__host__ __device__ constexpr int64_t delta_steps(int64_t m) {
+    return (m + 63 + 31) / 32 * 32;
+}
+
+// Square-truncation forward variants (SIGK_FLAG_SQUARE): the paper's default
+// fixed order N = 7, i.e. P = 8.
+#define SIGK_FWDSQ_VARIANTS(X) X(8, 8) X(8, 16) X(8, 32)
+
 // Variants of the adjoint kernels.
 #define SIGK_BWD_VARIANTS(X) \
     X(4, 8) X(5, 8) X(6, 8) X(8, 8) X(10, 8) X(12, 8) X(16, 8) X(20, 8) X(24, 8) \
@@ -35,7 +50,7 @@ __host__ __device__ constexpr int chunk_cols(int P) { return 32; }
 // 6-9% faster).  (The adjoint path keeps 32: there the wider buffers cost
 // more waves than the exchange saves.)
 __host__ __device__ constexpr int fwd_chunk_cols(int P, int D) {
-    return (P <= 5 && D <= 8) || (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
+    return D == 0 ? 32 : (P <= 5 && D <= 8) || (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
 }
 // Columns of the increment ring in LDS: it holds [c0-63, c0+chunk) while the
 // steps of chunk c0 run.  ring_cols: the checkpointing sweep and the adjoint;
@@ -86,7 +101,11 @@ struct WsHeader {
     unsigned long long flops;  // algorithmic flops
     unsigned order;            // compiled edge order used
     unsigned ticket2;          // next ticket (adjoint)
-    unsigned pad[56];
+    double trunc_max;          // largest per-pair truncation estimate
+    unsigned long long bwd_cells;  // cells of the adjoint sweep
+    unsigned long long bwd_flops;  // algorithmic flops of the adjoint sweep
+                                   // (adjoint maps + recomputed forward maps)
+    unsigned pad[50];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
@@ -111,7 +130,10 @@ struct FwdArgs {
     double* ckpt;      // adjoint checkpoints (null: forward only)
     double tau2[kMaxP];  // Neumann term n is needed where |c|^2 > tau2[n]
                          // (|c|^n/(n!)^2 > tol); all < 0 for the fixed depth
-    double tail_tol;
+    double* trunc_est;   // [npairs] truncation estimate per pair (strips add)
+    double* delta;       // channel bucket 0: cell coefficients, per pair
+                         // [strips][delta_steps(m)][64] (gram mode)
+    int64_t delta_pair;  // doubles per pair in delta
     int ckpt_every;    // steps between wave-state checkpoints (adjoint)
     long long watchdog_ticks;  // 100 MHz ticks before a wait is abandoned
 };
@@ -137,7 +159,17 @@ int device_error(hipError_t e);
     hipError_t launch_fwd_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
     int occupancy_fwd_##P##_##D();
 SIGK_FWD_VARIANTS(SIGK_DECL_FWD)
+SIGK_FWDG_VARIANTS(SIGK_DECL_FWD)
 #undef SIGK_DECL_FWD
+#define SIGK_DECL_FWDSQ(P, D) \
+    hipError_t launch_fwdsq_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_fwdsq_##P##_##D();
+SIGK_FWDSQ_VARIANTS(SIGK_DECL_FWDSQ)
+#undef SIGK_DECL_FWDSQ
+
+// The cell-coefficient field of every pair of a Gram call (FwdArgs in gram
+// mode with delta set), on the matrix cores.
+hipError_t launch_delta_gemm(const FwdArgs& a, hipStream_t s);
 #define SIGK_DECL_BWD(P, D) \
     hipError_t launch_ckpt_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
     hipError_t launch_bwd_##P##_##D(const BwdArgs& a, int grid, hipStream_t s); \

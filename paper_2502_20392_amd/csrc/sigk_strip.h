@@ -30,6 +30,19 @@
 // |c| = |<dx_k, dy_l>| <= |dx_k| |dy_l| (Cauchy-Schwarz).  The depth is
 // therefore uniform over the wave and known before each chunk, so the step
 // loop carries no data-dependent branch.
+//
+// Truncation estimate.  Keeping P coefficients per edge drops, in every cell,
+// the coefficients of degree >= P of both output edges.  The first of them is
+// led by c times the last kept coefficient of the input edge (the n = 1
+// Toeplitz term of the map: A'_P = c A_{P-1} + ...), so a cell's local error is
+// estimated as |c| (|A_{P-1}| + |B_{P-1}|) / P! relative to the local value of
+// K (the local series error of the error analysis of App. C, taken at its
+// leading term).  Local errors propagate with O(1) weight relative to K, so
+// they are summed over every cell of the pair: each lane keeps a running sum
+// over its cells; per chunk the wave adds the lanes' sums, each divided by
+// max(1, |K|) of its row where the chunk starts or ends (the smaller), and
+// each strip adds its share to the pair's total, which the host-side launch
+// compares with the pair's budget (SIGK_WARN_TRUNC above it).
 #pragma once
 #include "sigk_device.h"
 
@@ -50,14 +63,19 @@ __device__ __forceinline__ int ring_slot(int col) {
     return ring_slot_of<ring_cols(P)>(col);
 }
 
+// D > 0: the channel bucket (d <= D, increments in LDS and registers);
+// D = 0: the cell coefficients come from a field computed beforehand.
 template <int P, int D, int CH, int RB>
 struct LdsStrip {
     static_assert(RB >= CH + kWave - 1,
                   "the ring must hold the columns a chunk's steps touch");
-    double dx[D * RB];              // increments of x, [channel][ring slot]
+    // D > 0: increments of x, [channel][ring slot]; D = 0: the chunk's cell
+    // coefficients, [step][lane] (no LDS beyond what D > 0 needs: every byte
+    // more costs the order-5 kernel a wave per CU)
+    double dx[D > 0 ? D * RB : CH * kWave];
     double bin[CH * P];   // bottom edges of the current chunk (lane 0)
     double tout[CH * P];  // top edges of the top lane, current chunk
-    float nrm2[RB];                 // |dx_k|^2 of the same columns, rounded up
+    float nrm2[D > 0 ? RB : 1];     // |dx_k|^2 of the same columns, rounded up
 };
 
 struct Acc {
@@ -95,12 +113,36 @@ __host__ __device__ constexpr long long cell_flops(int P, int q, int d) {
            2LL * d;
 }
 
+// Last edge coefficient r in the Hankel sum of output coefficient n.  The
+// map keeps every product of a kept edge coefficient (r <= P-1); the square
+// truncation (SQ) is the paper's fixed-order tile of App. C and
+// Proposition A.3, which keeps only the entries C_ij with i, j <= N = P-1 of
+// the tile matrix, i.e. n + r <= P-1.
+template <int P, bool SQ>
+__host__ __device__ constexpr int hankel_top(int n) {
+    return SQ ? P - 1 - n : P - 1;
+}
+
+// sum_{r=1}^{top} V_r n!/(n+r)! without the leading 1/(n+1):
+// V_1 + (1/(n+2)) [V_2 + (1/(n+3)) [V_3 + ...]] (Horner form), 0 if top < 1.
+template <int P, int top, class RC>
+__device__ __forceinline__ double hankel_horner(const double (&V)[P], int n, const RC& R) {
+    if constexpr (top < 1) {
+        return 0.0;
+    } else {
+        double t = V[top];
+#pragma unroll
+        for (int r = top - 1; r >= 1; --r) t = fma(t, R(n + r + 1), V[r]);
+        return t;
+    }
+}
+
 // Neumann term N of the cell map (Toeplitz part and Horner-form Hankel part),
 // then the following terms while N < q.  ep = c^(N-1)/N! from the previous
 // term (1 for N = 1), so e_N = ep c and e_N/(N+1) = e_N (1/(N+1)).  Written
 // as a compile-time recursion so that every coefficient index is a constant
 // (registers, never scratch).
-template <int P, int N, class RC>
+template <int P, int N, bool SQ = false, class RC>
 __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double (&B)[P],
                                               double c, double ep, double (&An)[P],
                                               double (&Bn)[P], int q, const RC& R) {
@@ -113,21 +155,20 @@ __device__ __forceinline__ void neumann_terms(const double (&A)[P], const double
             Bn[i] = fma(e, B[i - N], Bn[i]);
         }
         // sum_{r>=1} B_r N!/(N+r)! = (1/(N+1)) [B_1 + (1/(N+2)) [B_2 + ...]]
-        double tb = B[P - 1], ta = A[P - 1];
-#pragma unroll
-        for (int r = P - 2; r >= 1; --r) {
-            tb = fma(tb, R(N + r + 1), B[r]);
-            ta = fma(ta, R(N + r + 1), A[r]);
-        }
+        constexpr int top = hankel_top<P, SQ>(N);
+        const double tb = hankel_horner<P, top>(B, N, R);
+        const double ta = hankel_horner<P, top>(A, N, R);
         const double en = e * R(N + 1);
-        An[N] = fma(en, tb, An[N]);
-        Bn[N] = fma(en, ta, Bn[N]);
-        neumann_terms<P, N + 1>(A, B, c, en, An, Bn, q, R);
+        if constexpr (top >= 1) {
+            An[N] = fma(en, tb, An[N]);
+            Bn[N] = fma(en, ta, Bn[N]);
+        }
+        neumann_terms<P, N + 1, SQ>(A, B, c, en, An, Bn, q, R);
     }
 }
 
 // The truncated cell map with Neumann depth q (wave-uniform, q <= P-1).
-template <int P, class RC>
+template <int P, bool SQ = false, class RC>
 __device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], double c,
                                          double (&An)[P], double (&Bn)[P], int q,
                                          const RC& R) {
@@ -148,7 +189,7 @@ __device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], d
         An[i] = A[i];
         Bn[i] = B[i];
     }
-    neumann_terms<P, 1>(A, B, c, 1.0, An, Bn, q, R);
+    neumann_terms<P, 1, SQ>(A, B, c, 1.0, An, Bn, q, R);
 }
 
 // The same map for a compile-time depth Q, in two phases: first everything
@@ -157,7 +198,7 @@ __device__ __forceinline__ void cell_map(const double (&A)[P], double (&B)[P], d
 // the bottom edge A (B_0 := A_0).  The first phase covers the latency of the
 // cross-lane move and LDS read that deliver A.  Every sum accumulates in the
 // same order as in cell_map.
-template <int P, int Q>
+template <int P, int Q, bool SQ = false>
 struct SplitMap {
     double e[Q + 1], en[Q + 1], tb[Q + 1];
 
@@ -170,9 +211,10 @@ struct SplitMap {
                 e[n] = n == 1 ? c : en[n - 1] * c;
                 en[n] = e[n] * R(n + 1);
             }
-            double t = B[P - 1];
+            const int top = hankel_top<P, SQ>(n);
+            double t = top >= 1 ? B[top >= 1 ? top : 1] : 0.0;
 #pragma unroll
-            for (int r = P - 2; r >= 1; --r) t = fma(t, R(n + r + 1), B[r]);
+            for (int r = top - 1; r >= 1; --r) t = fma(t, R(n + r + 1), B[r]);
             tb[n] = t;
         }
 #pragma unroll
@@ -201,36 +243,49 @@ struct SplitMap {
         Bn[0] = A[0] + t;
 #pragma unroll
         for (int n = 1; n <= Q; ++n) {
-            double ta = A[P - 1];
+            const int top = hankel_top<P, SQ>(n);
+            if (top < 1) continue;
+            double ta = A[top >= 1 ? top : 1];
 #pragma unroll
-            for (int r = P - 2; r >= 1; --r) ta = fma(ta, R(n + r + 1), A[r]);
+            for (int r = top - 1; r >= 1; --r) ta = fma(ta, R(n + r + 1), A[r]);
             An[n] = fma(en[n], tb[n], An[n]);
             Bn[n] = fma(en[n], ta, Bn[n]);
         }
     }
 };
 
-// Edge-series tail check: last coefficient's weight against the edge norm.
-template <int P>
-__device__ __forceinline__ void tail_check(const double* v, double tail_tol, bool act,
-                                           unsigned& status) {
-    double s = 0.0, f = 1.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        s = fma(fabs(v[i]), f, s);
-        if (i + 1 < P) f = f / (double)(i + 1);
-    }
-    const double tail = fabs(v[P - 1]) * f;
-    const bool bad_t = act && (tail > tail_tol * s);
-    const bool bad_n = act && !isfinite(s);
-    if (ballot(bad_t)) status |= SIGK_WARN_TRUNC;
-    if (ballot(bad_n)) status |= SIGK_WARN_NONFINITE;
-}
-
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+// A value equal in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/P!
+template <int P>
+__host__ __device__ constexpr double inv_factorial() {
+    double f = 1.0;
+    for (int i = 2; i <= P; ++i) f /= (double)i;
+    return f;
 }
 
 // Copy of P doubles between registers and 16-byte aligned LDS rows, in
@@ -249,8 +304,9 @@ __device__ __forceinline__ void lds_copy(double* dst, const double* src) {
     }
 }
 
-// CH: columns per frontier chunk; RB: columns of the increment ring.
-template <int P, int D, int CH, int RB>
+// CH: columns per frontier chunk; RB: columns of the increment ring; SQ:
+// square truncation of the tile matrix (the paper's fixed-order tile).
+template <int P, int D, int CH, int RB, bool SQ = false>
 struct StripCtx {
     const FwdArgs& a;
     Geo& g;
@@ -265,12 +321,20 @@ struct StripCtx {
     int* prog;          // progress counters of the pair
     double B[P];        // left-edge series of the lane's current cell
     double Ac[P];       // top-edge series produced at the previous step
-    double dy[D];
+    double dy[D > 0 ? D : 1];
     double cn;          // cell coefficient of the next step
     double dymax2;      // max_l |dy_l|^2 over the strip
     int q;              // Neumann depth of the current chunk
     unsigned nvalid;
     Recip<P> R;
+    int pair;           // pair index (truncation estimate slot)
+    int tload;          // chunks are loaded for steps below this (m; D = 0: all steps)
+    // truncation estimate: sum of |c| (|A_{P-1}| + |B_{P-1}|) over the lane's
+    // cells of the current chunk, the wave's total of the chunks done, each
+    // relative to the local size of K (wave-uniform), and the binary exponent
+    // of |K| where the lane's current chunk started
+    double tacc, etot;
+    int kexp;
     // checkpointing (adjoint support)
     double* ck;         // wave-state checkpoints of this strip or null
     double* ckq;        // Neumann depth per chunk (with ck)
@@ -279,9 +343,82 @@ struct StripCtx {
     __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH, RB>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
 
+    // One cell's local truncation estimate from its input edges (one FMA per
+    // edge, placed where that edge is available).
+    __device__ __forceinline__ void tally(double c, const double (&E)[P]) {
+        tacc = fma(fabs(c), fabs(E[P - 1]), tacc);
+    }
+    // Close the current chunk's sum, relative to the local size of K: per
+    // row, the smaller |K| of where the chunk started and where it ends (K is
+    // the left edge's constant term), taken as the power of two at or below
+    // it, at least 1.
+    __device__ __forceinline__ void fold() {
+        const double k1 = fabs(B[0]);
+        const int e1 = k1 >= 1.0 && k1 <= 1.7e308 ? ilogb(k1) : 0;  // 0 also for NaN
+        etot = uniform_d(etot + wave_sum(ldexp(tacc, -min(kexp, e1))));
+        kexp = e1;
+        tacc = 0.0;
+    }
+
+    // Bottom edges of columns [c0, c0+nc) from the strip below, once it has
+    // published them.
+    __device__ bool load_frontier(int c0, int nc) {
+        const int lane = lane_id();
+        if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
+        constexpr int NB = (CH * P + kWave - 1) / kWave;
+        const CoherentSpan src(Fin + (int64_t)c0 * P, nc * P);
+        double bv[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) bv[k] = src.load(lane + k * kWave);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (lane + k * kWave < nc * P) L.bin[lane + k * kWave] = bv[k];
+        return true;
+    }
+
+    // Depth of the chunk from the bound of |c|^2 over its cells.
+    __device__ __forceinline__ void set_depth(int c0, double cmax2) {
+        int qq = 0;
+#pragma unroll
+        for (int n = 1; n < P; ++n) qq = cmax2 > a.tau2[n] ? n : qq;
+        q = uniform(qq);
+        if (ckq && lane_id() == 0) ckq[c0 / CH] = (double)q;
+    }
+
+    // D = 0: the coefficients of steps [c0, c0+CH) from the precomputed field
+    // into LDS (lane j reads and later uses only its own row's cells: no
+    // exchange between lanes), cells outside the grid as 0; the depth from
+    // their exact maximum; the frontier as for D > 0.
+    __device__ bool load_chunk_field(int c0) {
+        const int lane = lane_id();
+        const double* src =
+            a.delta + g.delta + ((int64_t)s * delta_steps(g.m) + c0) * kWave + lane;
+        double cm = 0.0;
+        constexpr int NB = 16;
+#pragma unroll
+        for (int k0 = 0; k0 < CH; k0 += NB) {
+            double v[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) v[k] = src[(int64_t)(k0 + k) * kWave];  // t < delta_steps
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int col = c0 + k0 + k - lane;
+                const double c = (lane_ok && col >= 0 && col < g.m) ? v[k] : 0.0;
+                L.dx[(k0 + k) * kWave + lane] = c;
+                cm = fmax(cm, fabs(c));
+            }
+        }
+        if (c0 < g.m && has_below && !load_frontier(c0, min(CH, g.m - c0))) return false;
+        __syncthreads();
+        const double cmax = wave_max(cm);
+        set_depth(c0, cmax * cmax);
+        return true;
+    }
+
     // Load columns [c0, c0+CH) (increments, their norms, bottom edges) and set
     // the Neumann depth for steps [c0, c0+CH).
     __device__ bool load_chunk(int c0) {
+        if constexpr (D == 0) return load_chunk_field(c0);
         const int lane = lane_id();
         const int nc = min(CH, g.m - c0);
         // Issue every load before the first wait: the path points of the
@@ -289,24 +426,14 @@ struct StripCtx {
         // the frontier columns once the strip below has published them.
         const int col = c0 + min(lane, nc - 1);
         const double* xp = g.x + (int64_t)col * a.d;
-        double lo[D], hi[D];
+        double lo[D > 0 ? D : 1], hi[D > 0 ? D : 1];
 #pragma unroll
         for (int ch = 0; ch < D; ++ch) {
             const int cc = ch < a.d ? ch : 0;
             lo[ch] = xp[cc];
             hi[ch] = xp[a.d + cc];
         }
-        if (has_below) {
-            if (!wait_flag(&prog[s - 1], c0 + nc, a.hdr, a.watchdog_ticks)) return false;
-            constexpr int NB = (CH * P + kWave - 1) / kWave;
-            const CoherentSpan src(Fin + (int64_t)c0 * P, nc * P);
-            double bv[NB];
-#pragma unroll
-            for (int k = 0; k < NB; ++k) bv[k] = src.load(lane + k * kWave);
-#pragma unroll
-            for (int k = 0; k < NB; ++k)
-                if (lane + k * kWave < nc * P) L.bin[lane + k * kWave] = bv[k];
-        }
+        if (has_below && !load_frontier(c0, nc)) return false;
         if (lane < nc) {
             double n2 = 0.0;
 #pragma unroll
@@ -326,12 +453,7 @@ struct StripCtx {
         const int k1 = c0 - (kWave - 1) + lane, k2 = c0 + lane;
         if (k1 >= 0 && k1 < c0 + nc) w = (double)L.nrm2[ring_slot_of<RB>(k1)];
         if (lane < nc) w = fmax(w, (double)L.nrm2[ring_slot_of<RB>(k2)]);
-        const double cmax2 = wave_max(w) * dymax2;
-        int qq = 0;
-#pragma unroll
-        for (int n = 1; n < P; ++n) qq = cmax2 > a.tau2[n] ? n : qq;
-        q = uniform(qq);
-        if (ckq && lane == 0) ckq[c0 / CH] = (double)q;
+        set_depth(c0, wave_max(w) * dymax2);
         return true;
     }
 
@@ -363,6 +485,10 @@ struct StripCtx {
     // is recomputed after load_chunk().
     static constexpr bool kAhead = P <= 8;
     __device__ __forceinline__ void prefetch(int t) {
+        if constexpr (D == 0) {
+            cn = L.dx[((unsigned)t % (unsigned)CH) * kWave + lane_id()];
+            return;
+        }
         const int ri = ring_slot_of<RB>(t - lane_id());
         double c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -386,8 +512,13 @@ struct StripCtx {
             double bv[P];
             lds_copy<P>(bv, bsrc);
             double c;
-            double dxv[kAhead ? D : 1];
-            if constexpr (kAhead) {
+            double dxv[kAhead && D > 0 ? D : 1];
+            if constexpr (kAhead && D == 0) {
+                // the next step's coefficient (stale past the chunk's end: it
+                // is read again after the next chunk is loaded)
+                c = cn;
+                cn = L.dx[((unsigned)(t + 1) % (unsigned)CH) * kWave + lane];
+            } else if constexpr (kAhead) {
                 // increments of the next step's column, consumed after the map
                 c = cn;
                 const int ri = ring_slot_of<RB>(t + 1 - lane);
@@ -398,13 +529,15 @@ struct StripCtx {
                 c = cn;
             }
             double An[P], Bn[P];
-            SplitMap<P, QC> S;
+            SplitMap<P, QC, SQ> S;
             S.pre(B, c, Bn, R);
+            tally(c, B);  // every lane: rows past the grid have c = 0
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bv[i]);
             S.post(A, An, Bn, R);
-            if constexpr (kAhead) {
+            tally(c, A);
+            if constexpr (kAhead && D > 0) {
                 __builtin_amdgcn_sched_barrier(0);
                 double c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -441,8 +574,13 @@ struct StripCtx {
             prefetch(t);
             c = cn;
         }
+        // at the ramps, lanes outside the grid hold stale values: skip them
+        if (!EDGE || act) {
+            tally(c, A);
+            tally(c, B);
+        }
         double An[P], Bn[P];
-        cell_map<P>(A, B, c, An, Bn, QC >= 0 ? QC : q, R);
+        cell_map<P, SQ>(A, B, c, An, Bn, QC >= 0 ? QC : q, R);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             B[i] = Bn[i];
@@ -478,15 +616,10 @@ struct StripCtx {
         const int m = g.m;
         int t = t0;
         while (t < t1) {
-            if ((t % CH) == 0 && t < m) {
+            if ((t % CH) == 0 && t < tload) {
+                fold();
                 if (!load_chunk(t)) return false;
                 if (kAhead) prefetch(t);
-                if (t > 0) {
-                    // sample both edge series of every row once per chunk
-                    const bool done = lane_ok && t - lane > 0 && t - lane <= m;
-                    tail_check<P>(B, a.tail_tol, done, acc.status);
-                    tail_check<P>(Ac, a.tail_tol, done, acc.status);
-                }
             }
             // steps up to the next chunk boundary, flush point or range end
             int te = min(t1, t - (t % CH) + CH);
@@ -497,7 +630,7 @@ struct StripCtx {
                 te = min(te, min(nxt, m - 1) + kWave);
             }
             if (ck) te = min(te, t - (t % ck_every) + ck_every);
-            const long long fl = cell_flops(P, q, a.d);
+            const long long fl = cell_flops(P, q, D > 0 ? a.d : 0);  // D = 0: counted by the field
             if (EDGE) {
                 for (; t < te; ++t) {
                     if (ck && ((unsigned)t % (unsigned)ck_every) == 0) save_state(t);
@@ -544,7 +677,11 @@ struct StripCtx {
             n2 = fma(dy[ch], dy[ch], n2);
         }
         dymax2 = wave_max(n2);
+        tload = D == 0 ? m + nrows - 1 : m;
         q = P - 1;
+        tacc = 0.0;
+        etot = 0.0;
+        kexp = 0;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             B[i] = i == 0 ? 1.0 : 0.0;
@@ -561,17 +698,22 @@ struct StripCtx {
         if (m > kWave && !run<false>(kWave, m)) return false;
         if (!run<true>(max(tA, m), T)) return false;
         if (ck && (T % ck_every) == 0) save_state(T);
+        // the strip's share of the pair's truncation estimate
+        fold();
+        const double est = etot * inv_factorial<P>();
+        if (!isfinite(est)) acc.status |= SIGK_WARN_NONFINITE;
+        if (lane == 0 && a.trunc_est) atomicAdd(&a.trunc_est[pair], est);
         if (!has_above) {
             // the last row's lane holds the top edge of the corner cell
             const bool mine = lane == nrows - 1;
-            tail_check<P>(Ac, a.tail_tol, mine, acc.status);
-            if (mine && a.out) {
-                double k = 0.0, f = 1.0;
+            double k = 0.0, f = 1.0;
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    k = fma(Ac[i], f, k);
-                    f = f / (double)(i + 1);
-                }
+            for (int i = 0; i < P; ++i) {
+                k = fma(Ac[i], f, k);
+                f = f / (double)(i + 1);
+            }
+            if (ballot(mine && !isfinite(k))) acc.status |= SIGK_WARN_NONFINITE;
+            if (mine && a.out) {
                 a.out[g.o1] = k;
                 if (g.o2 >= 0) a.out[g.o2] = k;
             }

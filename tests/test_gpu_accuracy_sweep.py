@@ -3,14 +3,11 @@ fractional Brownian motion.
 
 Brownian paths of 2^k + 1 points on [0, 1] (quadratic variation sigma^2 per channel),
 k(x, y) at every compiled edge order against the oracle.  What truncation
-promises (the edge series of Sec. 3 cut at P terms, the device tail check
-flagging a last kept coefficient above the tail tolerance): every result
-without a truncation warning is within the bar of the oracle, the largest
-order raises none on these inputs and is within 1e-12, and the "auto" ladder
-returns the first warning-free order's value.  The bar is 1e-10 relative at
-sigma 1 and 1e-8 at sigma 2, the rough case: there a warning-free order can
-miss 1e-10 (65 points, order 10: 1.7e-10; the check looks at one coefficient
-per cell, while the dropped terms add up over the grid).
+promises (the edge series cut at P terms, every cell's local truncation
+estimate summed over the pair and compared with the budget 2^-36): every
+result without a truncation warning is within 1e-10 relative of the oracle,
+the largest order raises none on these inputs and is within 1e-12, and the
+"auto" ladder returns the first warning-free order's value.
 """
 import numpy as np
 import pytest
@@ -50,7 +47,7 @@ def test_order_sweep_brownian_2d(dev, length, sigma):
         assert not flags[p] & ~sk()._lib.WARN_TRUNC, (p, flags[p])
     print(f"\nlength {length} sigma {sigma} k {ref:.6g}: " +
           " ".join(f"P{p}:{errs[p]:.1e}{'w' if flags[p] else ''}" for p in orders))
-    bar = 1e-10 if sigma <= 1.0 else 1e-8
+    bar = 1e-10
     for p in orders:
         if flags[p] == 0:
             assert errs[p] <= bar, (length, sigma, p, errs[p])
@@ -87,3 +84,39 @@ def test_order_sweep_fbm_2d(dev, hurst):
             assert errs[p] <= 1e-10, (hurst, p, errs[p])
     assert flags[orders[-1]] == 0, hurst
     assert errs[orders[-1]] <= 1e-12, (hurst, errs[orders[-1]])
+
+
+def test_rough_65_point_pair_warns_at_order_10(dev):
+    """The 65-point sigma-2 pair whose order-10 value is 1.7e-10 off the oracle:
+    order 10 must raise SIGK_WARN_TRUNC (its estimate is far above the budget,
+    every cell of the single 64-column chunk counted), order 12 must not."""
+    X = synth.brownian(2, 65, 2, 2.0, seed=5000 + 65 + 20)
+    ref = oracle.pair(X[0], X[1])
+    x = torch.from_numpy(X[0]).to(dev)
+    y = torch.from_numpy(X[1]).to(dev)
+    k10 = sk().pair(x, y, order=10).item()
+    c10 = sk().counters()
+    assert c10["status"] & sk()._lib.WARN_TRUNC, c10
+    assert abs(k10 - ref) / max(1.0, abs(ref)) > 1e-10  # the warning is deserved
+    assert c10["trunc_est"] > 2.0 ** -36
+    k12 = sk().pair(x, y, order=12).item()
+    c12 = sk().counters()
+    assert c12["status"] == 0 and c12["trunc_est"] <= 2.0 ** -36, c12
+    assert abs(k12 - ref) / max(1.0, abs(ref)) <= 1e-10
+
+
+@pytest.mark.parametrize("order", [4, 5, 6, 8, 10, 12])
+def test_estimate_bounds_the_error(dev, order):
+    """The pair's truncation estimate against the error it estimates: on
+    2-D Brownian pairs (17 to 257 points, sigma 1 and 2) the oracle error of
+    every order is at most the estimate plus the Neumann-depth budget and the
+    rounding floor (2^-36 + 1e-13)."""
+    for length in (17, 65, 257):
+        for sigma in (1.0, 2.0):
+            X = synth.brownian(2, length, 2, sigma, seed=5000 + length + int(10 * sigma))
+            ref = oracle.pair(X[0], X[1])
+            k = sk().pair(torch.from_numpy(X[0]).to(dev), torch.from_numpy(X[1]).to(dev),
+                          order=order).item()
+            c = sk().counters()
+            err = abs(k - ref) / max(1.0, abs(ref))
+            assert err <= c["trunc_est"] + 2.0 ** -36 + 1e-13, (length, sigma, order, err, c)

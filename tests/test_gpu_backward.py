@@ -337,7 +337,7 @@ def test_mmd_gradient_wrt_y_and_both(dev):
 
 
 def test_one_call_entry_points(dev):
-    """sigk_gram_ragged and sigk_backward (plan, upload, run in one call) against
+    """sigk_gram_ragged and sigk_backward (one call on device tables) against
     the plan-based calls and the oracle."""
     pool, off, _ = synth.ragged_paths(n_paths=5, lmin=20, lmax=120, d=4, smin=0.3, smax=0.6)
     pairs = np.array([[0, 1], [2, 3], [4, 0], [3, 3]], dtype=np.int32)
@@ -349,4 +349,5 @@ def test_one_call_entry_points(dev):
     g = sk().backward(pd, off, pairs, T(w, dev), order=12).cpu().numpy()
     plan = sk().RaggedPlan(off, pairs, 4, order=12, device=dev)
     g2 = plan.backward(pd, T(w, dev)).cpu().numpy()
-    np.testing.assert_array_equal(g, g2)
+    # the same cell maps; only the order of the atomic gradient sums differs
+    assert np.abs(g - g2).max() <= 1e-13 * max(1.0, np.abs(g2).max())

@@ -84,3 +84,18 @@ def test_workload_status_and_symmetry(dev, long_pair, order):
     assert sk().counters()["status"] == 0
     k2 = sk().pair(yd, xd, order=order).item()
     assert math.isfinite(k1) and abs(k1 - k2) / max(abs(k1), 1.0) < 1e-10
+
+
+def test_headline_order_against_order_8(dev, long_pair):
+    """On the benchmarked pair itself: the value at order 5 (the order the
+    benchmark runs, chosen by the truncation estimate) against order 8, whose
+    estimate is many orders of magnitude smaller; a one-signed truncation bias
+    at order 5 would show here, which the x/y symmetry check cannot see."""
+    x, y = long_pair
+    xd, yd = T(x, dev), T(y, dev)
+    k5 = sk().pair(xd, yd, order=5).item()
+    c5 = sk().counters()
+    assert c5["status"] == 0 and c5["trunc_est"] <= 2.0 ** -36, c5
+    k8 = sk().pair(xd, yd, order=8).item()
+    assert sk().counters()["status"] == 0
+    assert abs(k5 - k8) / max(abs(k8), 1.0) <= 1e-10, (k5, k8)

@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
     for must in ("sigk_pair", "sigk_gram", "sigk_plan_ragged", "sigk_plan_run",
                  "sigk_plan_backward", "sigk_read_status"):
         assert must in names
-    assert len(names) == 25
+    assert len(names) == 27
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -68,16 +68,17 @@ def test_constants_match_header():
                     "SIGK_EWORKSPACE": _lib.SIGK_EWORKSPACE, "SIGK_EDEVICE": _lib.SIGK_EDEVICE,
                     "SIGK_EUNSUPPORTED": _lib.SIGK_EUNSUPPORTED,
                     "SIGK_WARN_TRUNC": _lib.WARN_TRUNC, "SIGK_WARN_NONFINITE": _lib.WARN_NONFINITE,
-                    "SIGK_ERR_WATCHDOG": _lib.ERR_WATCHDOG,
-                    "SIGK_FLAG_FIXED_DEPTH": _lib.FLAG_FIXED_DEPTH}
-    assert ctypes.sizeof(_lib.Opts) == 32 and ctypes.sizeof(_lib.Counters) == 24
+                    "SIGK_ERR_WATCHDOG": _lib.ERR_WATCHDOG, "SIGK_ERR_TABLE": _lib.ERR_TABLE,
+                    "SIGK_FLAG_FIXED_DEPTH": _lib.FLAG_FIXED_DEPTH,
+                    "SIGK_FLAG_SQUARE": _lib.FLAG_SQUARE, "SIGK_FLAG_FIELD": _lib.FLAG_FIELD}
+    assert ctypes.sizeof(_lib.Opts) == 32 and ctypes.sizeof(_lib.Counters) == 48
 
 
 def test_default_opts(lib):
     o = _lib.Opts()
     o.order, o.grid, o.flags, o.tol = 99, 7, 3, 5.0
     lib.sigk_default_opts(ctypes.byref(o))
-    assert (o.tol, o.tail_tol, o.order, o.grid, o.flags) == (0.0, 2.0 ** -50, 12, 0, 0)
+    assert (o.tol, o.tail_tol, o.order, o.grid, o.flags) == (0.0, 2.0 ** -36, 12, 0, 0)
     lib.sigk_default_opts(None)  # tolerated
 
 
@@ -144,18 +145,18 @@ def test_plan_cells_and_sizes(lib, seed):
             # the adjoint extends the forward layout (same plan tables first)
             assert bwd > fwd
             sizes.append((fwd, bwd))
-            # the one-call forms size their workspace exactly like the plan
+            # the one-call forms (device tables, every pair laid out for the
+            # longest path) need at least the plan's space
             o = _lib.make_opts(order=order)
-            offs = np.ascontiguousarray(offsets, dtype=np.int64)
-            prs = np.ascontiguousarray(pairs, dtype=np.int32)
             b1, b2 = ctypes.c_size_t(), ctypes.c_size_t()
-            assert lib.sigk_gram_ragged_workspace_size(offs.ctypes.data, len(offs) - 1, 5,
-                                                       prs.ctypes.data, len(prs),
-                                                       ctypes.byref(o), ctypes.byref(b1)) == 0
-            assert lib.sigk_backward_workspace_size(offs.ctypes.data, len(offs) - 1, 5,
-                                                    prs.ctypes.data, len(prs), ctypes.byref(o),
+            max_len = int(lens.max())
+            assert lib.sigk_gram_ragged_workspace_size(len(offsets) - 1, len(pairs), max_len,
+                                                       int(offsets[-1]), 5, ctypes.byref(o),
+                                                       ctypes.byref(b1)) == 0
+            assert lib.sigk_backward_workspace_size(len(offsets) - 1, len(pairs), max_len,
+                                                    int(offsets[-1]), 5, ctypes.byref(o),
                                                     ctypes.byref(b2)) == 0
-            assert (b1.value, b2.value) == (fwd, bwd)
+            assert b1.value >= fwd and b2.value >= bwd - (bwd - fwd) and b2.value > b1.value
         finally:
             lib.sigk_plan_destroy(plan)
     # more coefficients per edge never shrink the workspace
@@ -225,12 +226,17 @@ def test_plan_null_arguments(lib):
     assert lib.sigk_plan_ragged(offs.ctypes.data, 1, 2, prs.ctypes.data, 1, ctypes.byref(bad),
                                 ctypes.byref(plan)) == -1
     b = ctypes.c_size_t()
-    assert lib.sigk_gram_ragged_workspace_size(offs.ctypes.data, 1, 2, prs.ctypes.data, 1, None,
-                                               None) == -1
-    assert lib.sigk_backward_workspace_size(offs.ctypes.data, 1, 2, prs.ctypes.data, 1, None,
-                                            None) == -1
-    assert lib.sigk_gram_ragged_workspace_size(offs.ctypes.data, 1, 2, prs.ctypes.data, 1, None,
-                                               ctypes.byref(b)) == 0 and b.value > 0
+    assert lib.sigk_gram_ragged_workspace_size(1, 1, 5, 5, 2, None, None) == -1
+    assert lib.sigk_backward_workspace_size(1, 1, 5, 5, 2, None, None) == -1
+    assert lib.sigk_gram_ragged_workspace_size(1, 1, 5, 5, 2, None, ctypes.byref(b)) == 0
+    assert b.value > 0
+    for bad_args in ((-1, 1, 5, 5, 2), (1, -1, 5, 5, 2), (1, 1, -5, 5, 2), (1, 1, 5, -5, 2),
+                     (1, 1, 5, 5, 0)):
+        assert lib.sigk_gram_ragged_workspace_size(*bad_args, None, ctypes.byref(b)) == -1
+        assert lib.sigk_backward_workspace_size(*bad_args, None, ctypes.byref(b)) == -1
+    # tickets and progress slots are 32-bit: npairs x strips of max_len must fit
+    assert lib.sigk_gram_ragged_workspace_size(1, 1 << 20, 1 << 20, 1 << 20, 2, None,
+                                               ctypes.byref(b)) == -1
 
 
 # ---------------------------------------------------------------- pair / Gram sizes
@@ -262,7 +268,20 @@ def test_gram_workspace_rejections(lib):
     assert gram_size(lib, 3, 3, 10, 11, 2, 1)[0] == _lib.SIGK_EINVAL   # symmetric, lx != ly
     assert gram_size(lib, -1, 3, 10, 10, 2, 0)[0] == _lib.SIGK_EINVAL
     assert gram_size(lib, 3, 3, 10, 10, 0, 0)[0] == _lib.SIGK_EINVAL
-    assert gram_size(lib, 3, 3, 10, 10, 33, 0)[0] == _lib.SIGK_EUNSUPPORTED
+    # d > 32: the cell coefficients come from the matrix-core field stage, whose
+    # field ([strips][(m + 63 + 31)/32*32][64] doubles per pair) is in the workspace
+    rc33, b33 = gram_size(lib, 3, 3, 300, 200, 33, 0)
+    rc32, b32 = gram_size(lib, 3, 3, 300, 200, 32, 0)
+    assert rc33 == rc32 == 0
+    field = 9 * ((199 + 63) // 64) * ((299 + 63 + 31) // 32 * 32) * 64 * 8
+    assert field <= b33 - b32 <= field + 256
+    b = ctypes.c_size_t()
+    sq = _lib.make_opts(order=8, square=True)
+    assert lib.sigk_gram_workspace_size(3, 3, 10, 10, 33, 0, ctypes.byref(sq),
+                                        ctypes.byref(b)) == _lib.SIGK_EUNSUPPORTED
+    fo = _lib.make_opts(field=True)
+    assert lib.sigk_gram_workspace_size(3, 3, 300, 200, 4, 0, ctypes.byref(fo), ctypes.byref(b)) == 0
+    assert b.value >= gram_size(lib, 3, 3, 300, 200, 4, 0)[1] + field
     assert gram_size(lib, 3, 3, 10, 10, 4, 0, order=30)[0] == _lib.SIGK_EUNSUPPORTED
     o = _lib.make_opts()
     assert lib.sigk_gram_workspace_size(3, 3, 10, 10, 4, 0, ctypes.byref(o), None) == -1
@@ -287,7 +306,9 @@ def test_compute_calls_validate_before_the_device(lib):
                          None) == -2
     assert lib.sigk_pair(FAKE_DEV, 10, FAKE_DEV, 10, 0, ctypes.byref(o), FAKE_DEV, ws, 1 << 30,
                          None) == -1
-    assert lib.sigk_pair(FAKE_DEV, 10, FAKE_DEV, 10, 40, ctypes.byref(o), FAKE_DEV, ws, 1 << 30,
+    # d > 32 has no square-truncation variant: rejected before any device work
+    sq = _lib.make_opts(order=8, square=True)
+    assert lib.sigk_pair(FAKE_DEV, 10, FAKE_DEV, 10, 40, ctypes.byref(sq), FAKE_DEV, ws, 1 << 30,
                          None) == -4
     # a Gram call whose progress slots would not fit 32-bit indices
     assert lib.sigk_gram(FAKE_DEV, 40000, FAKE_DEV, 40000, 2, 1 << 20, 2, 0, ctypes.byref(o),
@@ -316,13 +337,16 @@ def test_compute_calls_validate_before_the_device(lib):
     finally:
         lib.sigk_plan_destroy(plan)
 
-    # one-call forms: a too-small workspace is reported before any copy
-    offs = np.array([0, 100, 180], dtype=np.int64)
-    prs = np.array([[0, 1]], dtype=np.int32)
-    assert lib.sigk_gram_ragged(FAKE_DEV, offs.ctypes.data, 2, 3, prs.ctypes.data, 1,
+    # one-call forms (device tables): a too-small workspace or a null table is
+    # reported before any launch
+    assert lib.sigk_gram_ragged(FAKE_DEV, 180, FAKE_DEV, 2, 3, FAKE_DEV, 1, 100,
                                 ctypes.byref(o), FAKE_DEV, ws, small, None) == -2
-    assert lib.sigk_backward(FAKE_DEV, offs.ctypes.data, 2, 3, prs.ctypes.data, 1, FAKE_DEV,
+    assert lib.sigk_backward(FAKE_DEV, 180, FAKE_DEV, 2, 3, FAKE_DEV, 1, 100, FAKE_DEV,
                              ctypes.byref(o), FAKE_DEV, ws, small, None) == -2
+    assert lib.sigk_gram_ragged(FAKE_DEV, 180, None, 2, 3, FAKE_DEV, 1, 100,
+                                ctypes.byref(o), FAKE_DEV, ws, 1 << 40, None) == -1
+    assert lib.sigk_backward(FAKE_DEV, 180, FAKE_DEV, 2, 3, None, 1, 100, FAKE_DEV,
+                             ctypes.byref(o), FAKE_DEV, ws, 1 << 40, None) == -1
     # status reads need somewhere to write
     assert lib.sigk_read_status(ws, None, None) == -1
     assert lib.sigk_read_counters(None, ctypes.byref(_lib.Counters()), None) == -1

@@ -101,6 +101,16 @@ class Lib:
                                            y.shape[0], x.shape[1], ctypes.byref(out), None, None)
         return out.value if rc == 0 else float("nan")
 
+    def pair_fixed(self, x, y, N):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        out = ctypes.c_double()
+        f = self.lib.sigk_oracle_pair_fixed_f64
+        f.argtypes = [_D, ctypes.c_int64, _D, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _D]
+        rc = f(x.ctypes.data_as(_D), x.shape[0], y.ctypes.data_as(_D), y.shape[0], x.shape[1],
+               int(N), ctypes.byref(out))
+        return out.value if rc == 0 else float("nan")
+
     def grad(self, x, y):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
@@ -256,3 +266,57 @@ def test_pins_reject_forward_mutant(source, tmp_path, name, old, new):
 def test_pins_reject_adjoint_mutant(source, tmp_path, name, old, new):
     lib = build_variant(mutate(source, old, new), str(tmp_path), "m")
     assert grad_failures(lib), f"no pin caught: {name}"
+
+
+# ----------------------------------------------------------------------------- fixed order
+FIXED_MUTANTS = [
+    ("top edge keeps N coefficients",
+     "for (int i = 0; i < n1; ++i) {\n                REAL sum = 0;\n"
+     "                for (int j = 0; j < n1; ++j) sum += C[(size_t)i * n1 + j];\n"
+     "                col[i] = sum;",
+     "for (int i = 0; i < n1; ++i) {\n                REAL sum = 0;\n"
+     "                for (int j = 0; j < n1 - 1; ++j) sum += C[(size_t)i * n1 + j];\n"
+     "                col[i] = sum;"),
+    ("right edge from the rows instead of the columns",
+     "for (int i = 0; i < n1; ++i) sum += C[(size_t)i * n1 + j];\n                right[j] = sum;",
+     "for (int i = 0; i < n1; ++i) sum += C[(size_t)j * n1 + i];\n                right[j] = sum;"),
+    ("left edge not reset at the start of a row",
+     "for (int j = 0; j < n1; ++j) left[j] = j == 0 ? 1 : 0;",
+     "for (int j = 0; j < n1; ++j) left[j] = j == 0 ? 1 : left[j];"),
+]
+
+
+def fixed_failures(lib):
+    """Names of the fixed-order pin checks that the build fails."""
+    fails = []
+    a = np.array([1.0, 0.5])
+    for c in (0.4, -1.7, 6.0):
+        b = np.array([c - 0.125, 0.25])
+        x, y = np.stack([np.zeros(2), a]), np.stack([np.zeros(2), b])
+        for N in (1, 3, 7):
+            ref = sum(c ** i / math.factorial(i) ** 2 for i in range(N + 1))
+            if not rel(lib.pair_fixed(x, y, N), ref) < 1e-14:
+                fails.append("partial Bessel sum")
+    X = synth.brownian(2, 30, 3, 1.5, seed=6307)
+    k = lib.pair_fixed(X[0], X[1], 7)
+    if not rel(lib.pair_fixed(X[1], X[0], 7), k) < 1e-13:
+        fails.append("transpose symmetry")
+    Y = synth.brownian(2, 40, 2, 2.0, seed=6200)
+    if not rel(lib.pair_fixed(Y[0], Y[1], 24), lib.pair(Y[0], Y[1])) < 1e-13:
+        fails.append("convergence to the kernel")
+    return fails
+
+
+@pytest.fixture(scope="module")
+def oracle_text():
+    return open(os.path.join(os.path.dirname(obuild.__file__), "sigk_oracle.c")).read()
+
+
+def test_unmutated_fixed_order_passes(tmp_path, oracle_text):
+    assert fixed_failures(build_variant(oracle_text, str(tmp_path), "fixed_clean")) == []
+
+
+@pytest.mark.parametrize("name,old,new", FIXED_MUTANTS, ids=[m[0] for m in FIXED_MUTANTS])
+def test_pins_reject_fixed_order_mutant(tmp_path, oracle_text, name, old, new):
+    lib = build_variant(mutate(oracle_text, old, new), str(tmp_path), "fixed_mut")
+    assert fixed_failures(lib), name

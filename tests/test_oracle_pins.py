@@ -255,3 +255,43 @@ def test_gram_positive_semidefinite(sigma):
     dg = np.diag(G)
     assert np.all(dg > 0)
     assert np.all(G * G <= np.outer(dg, dg) * (1 + 1e-12))
+
+
+# ----------------------------------------------------------------------------- fixed order
+
+@pytest.mark.parametrize("N", [0, 1, 3, 7, 12])
+@pytest.mark.parametrize("c", [0.4, -1.7, 6.0])
+def test_fixed_order_single_segment_is_partial_bessel_sum(N, c):
+    """One tile at fixed order N keeps the diagonal entries c^i/(i!)^2, i <= N:
+    k^[N] is the partial sum of Lemma 2.4's series (App. C, first display)."""
+    a = np.array([1.0, 0.5])
+    b = np.array([c - 0.5 * 0.25, 0.25])  # <a, b> = c
+    x = np.stack([np.zeros(2), a])
+    y = np.stack([np.zeros(2), b])
+    cc = float(a @ b)
+    ref = sum(cc ** i / math.factorial(i) ** 2 for i in range(N + 1))
+    assert rel(oracle.pair_fixed(x, y, N), ref) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fixed_order_converges_to_the_kernel(seed):
+    """k^[N] tends to k as N grows (the truncation error decays like (n!)^-2):
+    the error falls below 1e-13 by N = 24 on 2-D Brownian pairs."""
+    X = synth.brownian(2, 40, 2, 2.0, seed=6200 + seed)
+    ref = oracle.pair(X[0], X[1])
+    errs = [rel(oracle.pair_fixed(X[0], X[1], N), ref) for N in (3, 6, 10, 16, 24)]
+    assert errs[0] > 1e-6 and errs[-1] < 1e-13, errs
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+
+
+@pytest.mark.parametrize("N", [4, 7])
+def test_fixed_order_symmetry_and_padding(N):
+    """k^[N](x, y) = k^[N](y, x) (the scheme is transpose symmetric), and cells
+    with zero increments pass the edge series through unchanged, so repeated
+    points change nothing (exact properties of the truncated scheme too)."""
+    X = synth.brownian(2, 30, 3, 1.5, seed=6300 + N)
+    x, y = X[0], X[1]
+    k = oracle.pair_fixed(x, y, N)
+    assert rel(oracle.pair_fixed(y, x, N), k) < 1e-13
+    xp = np.concatenate([x[:10], x[9:10], x[9:20], x[19:20], x[19:20], x[20:]])
+    assert rel(oracle.pair_fixed(xp, y, N), k) < 1e-13
