@@ -282,6 +282,44 @@ int sigk_backward(const double* pool, int64_t pool_points, const int64_t* offset
                   int64_t max_len, const double* grad_out, const sigk_opts* o, double* grad_pool,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- long pair gradient */
+/*
+ * k(x, y) and its gradient for ONE pair with block (two-level) checkpointing,
+ * for pairs too long for per-strip checkpoints (memory of order
+ * (lx + ly) P sqrt(lx ly) instead of lx ly P):
+ *   grad_x[i][c] += grad_out[0] dk/dx[i][c],  grad_y[j][c] += grad_out[0] dk/dy[j][c].
+ * The derivative is the one sigk_backward computes (the exact adjoint of the
+ * truncated cell maps, chained through c_kl = <dx_k, dy_l>; Sec. 2.1, Prop.
+ * 2.5), evaluated in three stages on `stream`:
+ *   1. one forward sweep of the whole pair, which writes k(x, y) and keeps
+ *      the edge series on the boundaries of blocks of block_rows x block_cols
+ *      cells (the top edges of every block row's last row, the right edges of
+ *      every block column's last column);
+ *   2. block anti-diagonal by anti-diagonal, from the top-right corner down:
+ *      the forward sweep of each block recomputed from its boundary series
+ *      with per-strip checkpoints, then its adjoint sweep, which takes the
+ *      cotangents of the block's top and right edges from the blocks above
+ *      and to the right and leaves those of its bottom and left edges;
+ *   3. the chain to the points.
+ * x: [lx][d], y: [ly][d] (device, FP64); d <= 32.  grad_out (device) [1].
+ * k_out (device) [1] or NULL.  grad_x [lx][d], grad_y [ly][d] (device),
+ * ACCUMULATED.  block_rows: a multiple of 64, block_cols >= 1; 0 chooses a
+ * square block near sqrt(14.2 max(lx, ly)) (least workspace).  Truncation
+ * warnings of the forward sweep go to the status word as for sigk_pair.
+ * Allocates nothing, never synchronises.  ws: at least
+ * sigk_pair_backward_workspace_size bytes (host, same sizes);
+ * sigk_pair_backward_blocks (host) returns the block sizes used.
+ */
+int sigk_pair_backward_workspace_size(int64_t lx, int64_t ly, int64_t d, int64_t block_rows,
+                                      int64_t block_cols, const sigk_opts* o, size_t* bytes);
+int sigk_pair_backward_blocks(int64_t lx, int64_t ly, int64_t d, int64_t block_rows,
+                              int64_t block_cols, const sigk_opts* o, int64_t* rows_out,
+                              int64_t* cols_out);
+int sigk_pair_backward(const double* x, int64_t lx, const double* y, int64_t ly, int64_t d,
+                       const double* grad_out, int64_t block_rows, int64_t block_cols,
+                       const sigk_opts* o, double* k_out, double* grad_x, double* grad_y,
+                       void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- order estimate */
 /*
  * A-priori truncation order (App. C, "Error Analysis and Limitations": the

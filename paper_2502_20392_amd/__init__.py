@@ -4,5 +4,5 @@ gfx950) behind the C ABI of include/sigk.h; this package is its Python
 binding (PyTorch for device memory and streams) plus autograd wrappers."""
 from .api import (RaggedPlan, backward, counters, estimate_order, gram, gram_ragged,  # noqa: F401
                   gram_static, last_autograd_counters, last_workspace, mmd2, order_bound, pair,
-                  ragged, sigkernel_gram, workspace)
+                  pair_backward, pair_backward_workspace_size, ragged, sigkernel_gram, workspace)
 from . import _lib  # noqa: F401

@@ -92,6 +92,14 @@ SIGNATURES = {
     "sigk_plan_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_run_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_plan_backward_checkpointed": (ctypes.c_int, [_P, _P, _P, _P, _P, _SZ, _P]),
+    "sigk_pair_backward_workspace_size": (ctypes.c_int, [_I64, _I64, _I64, _I64, _I64,
+                                                         ctypes.POINTER(Opts),
+                                                         ctypes.POINTER(_SZ)]),
+    "sigk_pair_backward_blocks": (ctypes.c_int, [_I64, _I64, _I64, _I64, _I64,
+                                                 ctypes.POINTER(Opts), ctypes.POINTER(_I64),
+                                                 ctypes.POINTER(_I64)]),
+    "sigk_pair_backward": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _P, _I64, _I64,
+                                          ctypes.POINTER(Opts), _P, _P, _P, _P, _SZ, _P]),
     "sigk_order_bound": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]),

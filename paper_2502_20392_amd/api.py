@@ -10,6 +10,8 @@ stream; every arithmetic step runs in libsigk's HIP kernels.  Paths are
                             graph-capturable ``run``, and ``backward``.
 * ``ragged(pool, offsets, pairs)``  one-shot ragged batch.
 * ``gram_static(X, Y)``     Gram matrix through the library's static workspace.
+* ``pair_backward(x, y)``   k(x, y) and dk/dx, dk/dy of one long pair (block
+                            checkpointing).
 * ``counters(ws)``          cells, algorithmic flops and status of a call.
 
 ``order`` is the number of coefficients kept per edge series (P).  With
@@ -435,6 +437,55 @@ def backward(pool, offsets, pairs, grad_out, grad_pool=None, max_len=None, order
                                  _ptr(grad_pool), _ptr(w), w.numel(), _stream()))
     _tls.ws = w
     return grad_pool
+
+
+def pair_backward_workspace_size(lx, ly, d, order=12, block_rows=0, block_cols=0):
+    """(bytes, (block_rows, block_cols)) of sigk_pair_backward for these sizes (host only)."""
+    lib = _lib.load()
+    o = _lib.make_opts(order, None, None, 0, False)
+    nb = ctypes.c_size_t()
+    _lib.check(lib.sigk_pair_backward_workspace_size(lx, ly, d, block_rows, block_cols,
+                                                     ctypes.byref(o), ctypes.byref(nb)))
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _lib.check(lib.sigk_pair_backward_blocks(lx, ly, d, block_rows, block_cols, ctypes.byref(o),
+                                             ctypes.byref(r), ctypes.byref(c)))
+    return nb.value, (r.value, c.value)
+
+
+def pair_backward(x, y, grad_out=None, grad_x=None, grad_y=None, order=12, tol=None,
+                  tail_tol=None, grid=0, fixed_depth=False, block_rows=0, block_cols=0,
+                  ws=None):
+    """k(x, y) and its gradient for one (long) pair by block checkpointing
+    (sigk_pair_backward): grad_x += grad_out dk/dx, grad_y += grad_out dk/dy.
+    grad_out: a one-element CUDA tensor (default 1).  Returns (k, grad_x, grad_y)."""
+    x = _check_paths(x, "x", 2)
+    y = _check_paths(y, "y", 2)
+    if x.shape[1] != y.shape[1]:
+        raise ValueError("x and y must have the same number of channels")
+    dev = x.device
+    if grad_out is None:
+        grad_out = torch.ones(1, dtype=torch.float64, device=dev)
+    grad_out = _grad_out(grad_out, 1, dev)
+    if grad_x is None:
+        grad_x = torch.zeros_like(x)
+    if grad_y is None:
+        grad_y = torch.zeros_like(y)
+    _check_buffer(grad_x, "grad_x", x.numel(), dev, exact=True)
+    _check_buffer(grad_y, "grad_y", y.numel(), dev, exact=True)
+    lib = _lib.load()
+    o = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth)
+    nb = ctypes.c_size_t()
+    _lib.check(lib.sigk_pair_backward_workspace_size(x.shape[0], y.shape[0], x.shape[1],
+                                                     block_rows, block_cols, ctypes.byref(o),
+                                                     ctypes.byref(nb)))
+    w = _user_ws(ws, nb.value, dev)
+    k = torch.empty((), dtype=torch.float64, device=dev)
+    _lib.check(lib.sigk_pair_backward(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1],
+                                      _ptr(grad_out), block_rows, block_cols, ctypes.byref(o),
+                                      _ptr(k), _ptr(grad_x), _ptr(grad_y), _ptr(w), w.numel(),
+                                      _stream()))
+    _tls.ws = w
+    return k, grad_x, grad_y
 
 
 # ------------------------------------------------------------------ autograd

@@ -1107,3 +1107,245 @@ int sigk_backward(const double* pool, int64_t pool_points, const int64_t* offset
 }
 
 }  // extern "C"
+
+// ============================================================ long pair gradient
+namespace {
+
+struct LongLayout {
+    int P = 0, D = 0;
+    int64_t lx = 0, ly = 0, d = 0, m = 0, n = 0;
+    int rb = 0, cb = 0, ni = 0, nj = 0, kb = 0, nslots = 0, S = 0;
+    int64_t slot_snap = 0, slot_ckpt = 0;
+    int slot_prog = 0;
+    size_t o_est = 0, o_prog = 0, o_front = 0, o_hline = 0, o_vline = 0, o_snap = 0, o_ckpt = 0,
+           o_bprog = 0, o_lprog = 0, o_lamh = 0, o_lamv = 0, o_gdx = 0, o_scr = 0, total = 0;
+};
+
+// Square blocks of side b cost about 16 m n P / b bytes of lines and, per
+// anti-diagonal, min(m, n) b (9P/8) bytes of checkpoints and snapshots; the
+// sum is least near b = sqrt(14.2 max(m, n)).  Rows are rounded to whole
+// strips.
+int auto_block(int64_t m, int64_t n) {
+    const double b = std::sqrt(14.2 * (double)std::max(m, n));
+    const int r = (int)std::lround(b / 64.0) * 64;
+    return std::min(std::max(r, 64), 16384);
+}
+
+int long_layout(int64_t lx, int64_t ly, int64_t d, int64_t brows, int64_t bcols,
+                const sigk_opts& op, LongLayout& L) {
+    if (lx < 0 || ly < 0 || d < 1 || brows < 0 || bcols < 0 || (brows % kWave) != 0)
+        return SIGK_EINVAL;
+    if (lx > INT32_MAX / 2 || ly > INT32_MAX / 2 || brows > INT32_MAX / 2 ||
+        bcols > INT32_MAX / 2)
+        return SIGK_EINVAL;
+    L.P = round_order(op.order);
+    L.D = round_dim(d);
+    if (!L.P || !L.D || !find_bwd(L.P, L.D, op.flags)) return SIGK_EUNSUPPORTED;
+    const int P = L.P;
+    L.lx = lx;
+    L.ly = ly;
+    L.d = d;
+    L.m = std::max<int64_t>(lx - 1, 0);
+    L.n = std::max<int64_t>(ly - 1, 0);
+    const int64_t m = L.m, n = L.n;
+    const int64_t n64 = std::max<int64_t>((n + kWave - 1) / kWave * kWave, kWave);
+    L.rb = (int)std::min<int64_t>(brows ? brows : auto_block(m, n), n64);
+    L.cb = (int)std::max<int64_t>(std::min<int64_t>(bcols ? bcols : L.rb, std::max<int64_t>(m, 1)), 1);
+    L.ni = (int)std::max<int64_t>((n + L.rb - 1) / L.rb, 1);
+    L.nj = (int)std::max<int64_t>((m + L.cb - 1) / L.cb, 1);
+    L.kb = L.rb / kWave;
+    L.nslots = std::min(L.ni, L.nj);
+    L.S = (int)((n + kWave - 1) / kWave);
+    L.slot_snap = (int64_t)L.kb * L.cb * P;
+    L.slot_ckpt = (int64_t)L.kb * ckpt_strip_doubles(L.cb, P);
+    L.slot_prog = L.kb + 2;
+    if ((int64_t)L.nslots * L.kb > INT32_MAX || (int64_t)L.nslots * L.slot_prog > INT32_MAX)
+        return SIGK_EINVAL;
+    size_t o = align256(sizeof(WsHeader));
+    auto take = [&o](size_t& at, size_t bytes) {
+        at = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+    };
+    take(L.o_est, sizeof(double));
+    take(L.o_prog, sizeof(int) * (size_t)L.S);
+    take(L.o_front, sizeof(double) * (size_t)(m * P));
+    take(L.o_hline, sizeof(double) * (size_t)((L.ni - 1) * m * P));
+    take(L.o_vline, sizeof(double) * (size_t)((L.nj - 1) * n * P));
+    take(L.o_snap, sizeof(double) * (size_t)(L.nslots * L.slot_snap));
+    take(L.o_ckpt, sizeof(double) * (size_t)(L.nslots * L.slot_ckpt));
+    take(L.o_bprog, sizeof(int) * (size_t)L.nslots * L.slot_prog);
+    take(L.o_lprog, sizeof(int) * (size_t)L.nslots * L.slot_prog);
+    take(L.o_lamh, sizeof(double) * (size_t)(m * P));
+    take(L.o_lamv, sizeof(double) * (size_t)(n * P));
+    take(L.o_gdx, sizeof(double) * (size_t)((lx + ly) * d));
+    take(L.o_scr, sizeof(double) * (size_t)kBwdMaxGrid * kCkptEvery * P * kWave);
+    L.total = o;
+    return SIGK_OK;
+}
+
+// Before the blocks of one anti-diagonal: both ticket counters, and per slot
+// the progress counters of the checkpointing sweep and of the adjoint, each
+// between two sentinels that count as complete (strip 0 reads a bottom line,
+// the top strip a cotangent row, with no producer in the launch).
+__global__ void blk_diag_reset_kernel(WsHeader* h, int* bprog, int* lprog, int n, int per) {
+    const int i0 = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 == 0) {
+        h->ticket = 0;
+        h->ticket2 = 0;
+    }
+    for (int i = i0; i < n; i += (int)(gridDim.x * blockDim.x)) {
+        const int k = i % per;
+        const int v = (k == 0 || k == per - 1) ? INT32_MAX : 0;
+        bprog[i] = v;
+        lprog[i] = v;
+    }
+}
+
+// dL/dz from dL/d(dz) for the two paths stored back to back in gdx (x's
+// increments at its points 0..lx-2, y's after lx points), accumulated.
+__global__ void chain2_kernel(const double* gdx, int64_t lx, int64_t ly, int d, double* gx,
+                              double* gy) {
+    const int64_t nx = lx * d, n = (lx + ly) * d;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < n; i += stride) {
+        const bool isx = i < nx;
+        const int64_t j = isx ? i : i - nx;  // index within the path
+        const double prev = j >= d ? gdx[i - d] : 0.0;
+        const double last = (isx ? j >= nx - d : j >= n - nx - d) ? 0.0 : gdx[i];
+        double* g = isx ? gx : gy;
+        g[j] += prev - last;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sigk_pair_backward_workspace_size(int64_t lx, int64_t ly, int64_t d, int64_t block_rows,
+                                      int64_t block_cols, const sigk_opts* o, size_t* bytes) {
+    if (!bytes || !valid_opts(o)) return SIGK_EINVAL;
+    LongLayout L;
+    const int rc = long_layout(lx, ly, d, block_rows, block_cols, opts_or_default(o), L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return SIGK_OK;
+}
+
+int sigk_pair_backward_blocks(int64_t lx, int64_t ly, int64_t d, int64_t block_rows,
+                              int64_t block_cols, const sigk_opts* o, int64_t* rows_out,
+                              int64_t* cols_out) {
+    if (!rows_out || !cols_out || !valid_opts(o)) return SIGK_EINVAL;
+    LongLayout L;
+    const int rc = long_layout(lx, ly, d, block_rows, block_cols, opts_or_default(o), L);
+    if (rc) return rc;
+    *rows_out = L.rb;
+    *cols_out = L.cb;
+    return SIGK_OK;
+}
+
+int sigk_pair_backward(const double* x, int64_t lx, const double* y, int64_t ly, int64_t d,
+                       const double* grad_out, int64_t block_rows, int64_t block_cols,
+                       const sigk_opts* o, double* k_out, double* grad_x, double* grad_y,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_opts(o)) return SIGK_EINVAL;
+    const sigk_opts op = opts_or_default(o);
+    LongLayout L;
+    int rc = long_layout(lx, ly, d, block_rows, block_cols, op, L);
+    if (rc) return rc;
+    if (!ws || !grad_out || (lx > 0 && (!x || !grad_x)) || (ly > 0 && (!y || !grad_y)))
+        return SIGK_EINVAL;
+    if (ws_bytes < L.total) return SIGK_EWORKSPACE;
+    const Variant* v = find_bwd(L.P, L.D);
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    WsHeader* hdr = (WsHeader*)base;
+    int* prog = (int*)(base + L.o_prog);
+    double* est = (double*)(base + L.o_est);
+    hipError_t e = launch_reset(hdr, prog, L.S, k_out, k_out ? 1 : 0, est, 1, (unsigned)L.P, s);
+    if (e != hipSuccess) return device_error(e);
+    if (L.m == 0 || L.n == 0) return SIGK_OK;  // k = 1 for every path: no gradient
+    double* gdx = (double*)(base + L.o_gdx);
+    const int64_t ngdx = (lx + ly) * d;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ngdx)), dim3(256), 0, s, nullptr, 0, gdx,
+                       ngdx);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+
+    FwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_common(a, op, L.P, d, L.m * L.n);
+    a.X = x;
+    a.Y = y;
+    a.npairs = 1;
+    a.hdr = hdr;
+    BlockGeo& k = a.blk;
+    k.m = L.m;
+    k.n = L.n;
+    k.rb = L.rb;
+    k.cb = L.cb;
+    k.ni = L.ni;
+    k.nj = L.nj;
+    k.kb = L.kb;
+    k.hline = (double*)(base + L.o_hline);
+    k.vline = (double*)(base + L.o_vline);
+    k.slot_snap = L.slot_snap;
+    k.slot_ckpt = L.slot_ckpt;
+    k.slot_prog = L.slot_prog;
+    k.y_gdx = lx * d;
+    const int cgrid = std::max(device_wgs(L.P, L.D, kKernelCkpt), 1);
+    const int bgrid = std::min(std::max(device_wgs(L.P, L.D, kKernelBwd), 1), kBwdMaxGrid);
+
+    // 1. the whole pair once: k(x, y), its truncation estimate and the lines
+    a.mode = kModeLines;
+    a.ntickets = L.S;
+    a.out = k_out;
+    a.frontier = (double*)(base + L.o_front);
+    a.progress = prog;
+    a.trunc_est = est;
+    e = v->ckpt(a, (int)std::min<int64_t>(cgrid, L.S), s);
+    if (e == hipSuccess) e = launch_finalize(hdr, est, 1, budget_of(op), s);
+    if (e != hipSuccess) return device_error(e);
+
+    // 2. block anti-diagonals from the top-right corner down: checkpoints of
+    // the blocks, then their adjoint
+    a.mode = kModeBlock;
+    a.out = nullptr;
+    a.trunc_est = nullptr;
+    a.frontier = (double*)(base + L.o_snap);
+    a.ckpt = (double*)(base + L.o_ckpt);
+    a.progress = (int*)(base + L.o_bprog);
+    BwdArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.grad_out = grad_out;
+    b.snap = a.frontier;
+    b.ckpt = a.ckpt;
+    b.lam_front = (double*)(base + L.o_lamh);
+    b.lam_v = (double*)(base + L.o_lamv);
+    b.lam_prog = (int*)(base + L.o_lprog);
+    b.gdx = gdx;
+    b.scratch = (double*)(base + L.o_scr);
+    for (int diag = L.ni + L.nj - 2; diag >= 0; --diag) {
+        const int j_lo = std::max(0, diag - (L.ni - 1));
+        const int j_hi = std::min(diag, L.nj - 1);
+        k.diag = diag;
+        k.j_lo = j_lo;
+        k.nb = j_hi - j_lo + 1;
+        const int nprog = k.nb * L.slot_prog;
+        hipLaunchKernelGGL(blk_diag_reset_kernel, dim3((nprog + 255) / 256), dim3(256), 0, s, hdr,
+                           a.progress, b.lam_prog, nprog, L.slot_prog);
+        if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+        a.ntickets = (int64_t)k.nb * L.kb;
+        e = v->ckpt(a, (int)std::min<int64_t>(cgrid, a.ntickets), s);
+        if (e != hipSuccess) return device_error(e);
+        b.f = a;
+        b.ntickets = a.ntickets;
+        e = v->bwd(b, (int)std::min<int64_t>(bgrid, b.ntickets), s);
+        if (e != hipSuccess) return device_error(e);
+    }
+    hipLaunchKernelGGL(chain2_kernel, dim3(blocks_for(ngdx)), dim3(256), 0, s, gdx, lx, ly,
+                       (int)d, grad_x, grad_y);
+    if ((e = hipGetLastError()) != hipSuccess) return device_error(e);
+    return SIGK_OK;
+}
+
+}  // extern "C"

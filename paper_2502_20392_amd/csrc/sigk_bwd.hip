@@ -12,10 +12,15 @@
 //                segment forward while storing each step's bottom-edge inputs
 //                in a per-workgroup scratch, then run the adjoint cell map over
 //                the segment in reverse step order, recovering each cell's left
-//                edge from its right edge (the left-edge update is triangular).  dL/dc of every cell is chained
-//                into dL/d(increment) of both paths: the x side through an LDS
-//                ring indexed by column (each column is complete once lane 0 has
+//                edge from its right edge (the left-edge update is
+//                triangular).  dL/dc of every cell is chained into
+//                dL/d(increment) of both paths: the x side through an LDS ring
+//                indexed by column (each column is complete once lane 0 has
 //                passed it), the y side in registers of the row's lane.
+// Both also run the blocks of a long pair (block checkpointing, see BlockGeo):
+// a block is a small pair whose bottom and left edges come from lines kept by
+// a first sweep and whose top and right edge cotangents come from the blocks
+// processed before it.
 #include "sigk_adjoint.h"
 
 #ifndef SIGK_P
@@ -34,6 +39,12 @@ namespace sigk {
 template <int P, int D>
 constexpr int ckpt_chunk = (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
 
+// Modes: kModeTable, the checkpointing sweep of a batch (snap: per-strip
+// frontier rows); kModeLines, the plain sweep of one long pair keeping the
+// block-boundary lines (snap: the in-place frontier row, no checkpoints);
+// kModeBlock, the checkpointing sweep of the blocks of one anti-diagonal
+// (snap: per-slot frontier rows; strip 0 reads its bottom line, column 0
+// its left line).
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
     constexpr int CH = ckpt_chunk<P, D>, RB = CH == 64 ? 128 : ring_cols(P);
@@ -46,20 +57,55 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
         t = (unsigned)uniform((int)t);
         if ((int64_t)t >= a.ntickets) break;
         if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
-        const int pair = a.tickets[t].pair, strip = a.tickets[t].strip;
-        if (pair < 0) break;  // unused slots close a table built on the device
-        Geo g = resolve(a, pair, P, 0);
-        const PairDesc& pd = a.desc[pair];
-        StripCtx<P, D, CH, RB> S(a, g, L, acc, strip);
+        int pair, strip;
+        Geo g;
+        BlockRef r;
+        r.bot = nullptr;
+        r.left = nullptr;
+        if (a.mode == kModeTable) {
+            pair = a.tickets[t].pair;
+            strip = a.tickets[t].strip;
+            if (pair < 0) break;  // unused slots close a table built on the device
+            g = resolve(a, pair, P, 0);
+            g.front = a.desc[pair].snap_off;
+        } else if (a.mode == kModeLines) {
+            pair = 0;
+            strip = (int)t;
+            g = resolve_lines(a);
+        } else {
+            pair = (int)(t % (unsigned)a.blk.nb);
+            strip = (int)(t / (unsigned)a.blk.nb);
+            g = resolve_block(a, pair, P, r);
+            if (strip * kWave >= g.n) continue;  // the top block row has fewer strips
+        }
+        StripCtx<P, D, CH, RB, false, true> S(a, g, L, acc, strip);
         S.pair = pair;
-        const int64_t row = (int64_t)g.m * P;
-        S.Fin = snap + pd.snap_off + (int64_t)strip * row;
-        S.Fout = snap + pd.snap_off + (int64_t)(strip + 1) * row;
         S.prog = a.progress + g.prog;
-        double* ck = a.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
-        S.ck = ck;
-        S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
-        S.ck_every = kCkptEvery;
+        const int64_t row = (int64_t)g.m * P;
+        if (a.mode == kModeLines) {
+            // in-place frontier row, except across block-row boundaries
+            const int kb = a.blk.kb;
+            double* own = snap;
+            S.Fin = (strip > 0 && strip % kb == 0)
+                        ? a.blk.hline + (int64_t)(strip / kb - 1) * row
+                        : own;
+            S.Fout = ((strip + 1) % kb == 0 && (int64_t)(strip + 1) * kWave < g.n)
+                         ? a.blk.hline + (int64_t)((strip + 1) / kb - 1) * row
+                         : own;
+            S.ck = nullptr;
+            S.ckq = nullptr;
+            S.ck_every = 1;
+            S.vl = a.blk.nj > 1 ? a.blk.vline : nullptr;
+        } else {
+            S.Fin = (strip == 0 && r.bot) ? r.bot : snap + g.front + (int64_t)strip * row;
+            S.Fout = snap + g.front + (int64_t)(strip + 1) * row;
+            double* ck = a.ckpt + g.ckpt + (int64_t)strip * ckpt_strip_doubles(g.m, P);
+            S.ck = ck;
+            S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
+            S.ck_every = kCkptEvery;
+            S.left = r.left;
+            S.below_line = r.bot != nullptr;
+        }
         if (!S.sweep()) break;
     }
     if (lane == 0) {
@@ -98,7 +144,6 @@ struct StripBwd {
     LdsBwd<P, D>& L;
     int s, nrows, m;
     bool lane_ok, has_below, has_above;
-    const PairDesc* pd;
     double dy[D];
     double gy[D];
     Recip<P, false> R;  // scalar or rematerialised constants: registers are scarce here
@@ -111,7 +156,20 @@ struct StripBwd {
     const double* snap_in;   // primal frontier row read by lane 0 ([m][P])
     double* lam_row;         // adjoint frontier row of the pair ([m][P])
     int* lam_prog;           // adjoint progress of the pair's strips
-    double seed_scale;       // grad_out of the pair
+    double seed_scale;       // grad_out of the pair (0: no seed in this grid)
+    double* gxp;             // dL/d(dx) of the pair's columns ([m][d])
+    double* gyp;             // dL/d(dy) of the pair's rows ([n][d])
+    // block checkpointing (null / false for whole pairs): primal left edges at
+    // column 0, a primal bottom line for strip 0 and a cotangent row from a
+    // block above; the right-edge cotangents of the rows (read at the last
+    // column when a block to the right exists, written at column 0 when one
+    // to the left does)
+    const double* left = nullptr;
+    bool below_line = false;
+    bool above_blk = false;
+    double* lamv = nullptr;
+    bool right_in = false;
+    bool left_out = false;
 
     __device__ StripBwd(const BwdArgs& b_, Geo& g_, LdsBwd<P, D>& L_, int s_)
         : b(b_), a(b_.f), g(g_), L(L_), s(s_) {}
@@ -188,7 +246,7 @@ struct StripBwd {
         if (lane < nc) {
             const int col = c0 + lane;
             const int sl = ring_slot_of<ARB>(col);
-            double* gp = b.gdx + pd->x_off + (int64_t)col * a.d;
+            double* gp = gxp + (int64_t)col * a.d;
 #pragma unroll
             for (int ch = 0; ch < D; ++ch) {
                 if (ch < a.d) atomicAdd(&gp[ch], L.gx[ch * ARB + sl]);
@@ -245,8 +303,14 @@ struct StripBwd {
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
             if (col == 0) {
+                if (left != nullptr && lane_ok) {
+                    const double* lp = left + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
-                for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+                    for (int i = 0; i < P; ++i) B[i] = lp[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+                }
             }
             double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
 #pragma unroll
@@ -317,16 +381,30 @@ struct StripBwd {
                 }
             }
             if (col == m - 1) {
+                if (right_in && lane_ok) {
+                    const double* lp = lamv + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
-                for (int i = 0; i < P; ++i) lBst[i] = 0.0;
+                    for (int i = 0; i < P; ++i) lBst[i] = lp[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) lBst[i] = 0.0;
+                }
             }
+            // column 0 on a left line: the left edge is recovered like any
+            // other (it is the right edge of the block to the left)
+            const bool axis = col == 0 && left == nullptr;
             double lA[P], lB[P];
             double gc;
             if constexpr (Q >= 0)
-                gc = cell_adjoint_fixed<P, Q>(A, B, c, col == 0, col < m, lAo, lBst, lA, lB, R);
+                gc = cell_adjoint_fixed<P, Q>(A, B, c, axis, col < m, lAo, lBst, lA, lB, R);
             else
-                gc = cell_adjoint<P>(A, B, c, q, col == 0, col < m, lAo, lBst, lA, lB, R);
+                gc = cell_adjoint<P>(A, B, c, q, axis, col < m, lAo, lBst, lA, lB, R);
             if (!act) gc = 0.0;
+            if (left_out && act && col == 0) {
+                double* lp = lamv + ((int64_t)s * kWave + lane) * P;
+#pragma unroll
+                for (int i = 0; i < P; ++i) lp[i] = lB[i];
+            }
 #pragma unroll
             for (int ch = 0; ch < D; ++ch) gy[ch] = fma(gc, dxv[ch], gy[ch]);
             if (act) {
@@ -356,8 +434,8 @@ struct StripBwd {
         const int row0 = s * kWave;
         nrows = min(kWave, g.n - row0);
         lane_ok = lane < nrows;
-        has_below = s > 0;
-        has_above = row0 + kWave < g.n;
+        has_below = s > 0 || below_line;
+        has_above = row0 + kWave < g.n || above_blk;
         R.init();
         const int l = row0 + lane;
 #pragma unroll
@@ -398,7 +476,7 @@ struct StripBwd {
         }
         // dL/d(dy_l) of this lane's row
         if (lane_ok) {
-            double* gp = b.gdx + pd->y_off + (int64_t)l * a.d;
+            double* gp = gyp + (int64_t)l * a.d;
 #pragma unroll
             for (int ch = 0; ch < D; ++ch)
                 if (ch < a.d) atomicAdd(&gp[ch], gy[ch]);
@@ -421,21 +499,52 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
         t = (unsigned)uniform((int)t);
         if ((int64_t)t >= b.ntickets) break;
         if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
-        const int pair = b.tickets[t].pair, strip = b.tickets[t].strip;
-        if (pair < 0) break;  // unused slots close a table built on the device
-        Geo g = resolve(a, pair, P, 0);
-        const PairDesc& pd = a.desc[pair];
+        int pair, strip;
+        Geo g;
+        BlockRef r;
+        if (a.mode == kModeTable) {
+            pair = b.tickets[t].pair;
+            strip = b.tickets[t].strip;
+            if (pair < 0) break;  // unused slots close a table built on the device
+            g = resolve(a, pair, P, 0);
+        } else {
+            // kModeBlock: the blocks of one anti-diagonal, strips top-down
+            pair = (int)(t % (unsigned)a.blk.nb);
+            strip = a.blk.kb - 1 - (int)(t / (unsigned)a.blk.nb);
+            g = resolve_block(a, pair, P, r);
+            if (strip * kWave >= g.n) continue;  // the top block row has fewer strips
+        }
         StripBwd<P, D> S(b, g, L, strip);
-        S.pd = &pd;
         S.scratch = scratch;
         S.cells = &cells;
         S.flops = &flops;
-        S.ck = b.ckpt + pd.ckpt_off + (int64_t)strip * ckpt_strip_doubles(g.m, P);
+        S.ck = b.ckpt + g.ckpt + (int64_t)strip * ckpt_strip_doubles(g.m, P);
         S.ckq = S.ck + ckpt_states(g.m) * 2 * P * kWave;
-        S.snap_in = b.snap + pd.snap_off + (int64_t)strip * g.m * P;
-        S.lam_row = b.lam_front + pd.front_off;
-        S.lam_prog = b.lam_prog + pd.prog_off;
-        S.seed_scale = b.grad_out[pair];
+        if (a.mode == kModeTable) {
+            const PairDesc& pd = a.desc[pair];
+            S.snap_in = b.snap + pd.snap_off + (int64_t)strip * g.m * P;
+            S.lam_row = b.lam_front + pd.front_off;
+            S.lam_prog = b.lam_prog + pd.prog_off;
+            S.seed_scale = b.grad_out[pair];
+            S.gxp = b.gdx + pd.x_off;
+            S.gyp = b.gdx + pd.y_off;
+        } else {
+            const BlockGeo& k = a.blk;
+            S.snap_in = (strip == 0 && r.bot) ? r.bot
+                                              : b.snap + g.front + (int64_t)strip * g.m * P;
+            S.lam_row = b.lam_front + (int64_t)r.J * k.cb * P;
+            S.lam_prog = b.lam_prog + g.prog;
+            // the grid's corner cell belongs to the top-right block
+            S.seed_scale = (!r.above && !r.right) ? b.grad_out[0] : 0.0;
+            S.gxp = b.gdx + (int64_t)r.J * k.cb * a.d;
+            S.gyp = b.gdx + k.y_gdx + (int64_t)r.I * k.rb * a.d;
+            S.left = r.left;
+            S.below_line = r.bot != nullptr;
+            S.above_blk = r.above;
+            S.lamv = b.lam_v + (int64_t)r.I * k.rb * P;
+            S.right_in = r.right;
+            S.left_out = r.J > 0;
+        }
         if (!S.sweep()) break;
     }
     if (lane == 0) {

@@ -175,4 +175,54 @@ __device__ Geo resolve(const FwdArgs& a, int pair, int P, int64_t ckpt_per_pair)
     return g;
 }
 
+// kModeLines: the whole pair (X = x, Y = y), one output.
+__device__ __forceinline__ Geo resolve_lines(const FwdArgs& a) {
+    Geo g;
+    g.x = a.X;
+    g.y = a.Y;
+    g.m = (int)a.blk.m;
+    g.n = (int)a.blk.n;
+    g.front = 0;
+    g.ckpt = 0;
+    g.delta = 0;
+    g.prog = 0;
+    g.o1 = 0;
+    g.o2 = -1;
+    return g;
+}
+
+// Boundary data of a block in kModeBlock (null where the block touches the
+// axes, i.e. its bottom or left edge is the constant 1).
+struct BlockRef {
+    int I, J;           // block row and column
+    const double* bot;  // primal bottom edges of its columns ([cb][P])
+    const double* left; // primal left edges of its rows ([rb][P])
+    bool above, right;  // a block above / to the right exists
+};
+
+// Block of slot `slot` on the launch's anti-diagonal: a sub-pair of the paths
+// with its own strips, snapshots, checkpoints and progress counters.
+__device__ __forceinline__ Geo resolve_block(const FwdArgs& a, int slot, int P, BlockRef& r) {
+    const BlockGeo& k = a.blk;
+    const int J = k.j_lo + slot, I = k.diag - J;
+    Geo g;
+    g.x = a.X + (int64_t)J * k.cb * a.d;
+    g.y = a.Y + (int64_t)I * k.rb * a.d;
+    g.m = (int)(k.m - (int64_t)J * k.cb < k.cb ? k.m - (int64_t)J * k.cb : k.cb);
+    g.n = (int)(k.n - (int64_t)I * k.rb < k.rb ? k.n - (int64_t)I * k.rb : k.rb);
+    g.front = (int64_t)slot * k.slot_snap;
+    g.ckpt = (int64_t)slot * k.slot_ckpt;
+    g.delta = 0;
+    g.prog = slot * k.slot_prog + 1;
+    g.o1 = -1;
+    g.o2 = -1;
+    r.I = I;
+    r.J = J;
+    r.bot = I > 0 ? k.hline + ((int64_t)(I - 1) * k.m + (int64_t)J * k.cb) * P : nullptr;
+    r.left = J > 0 ? k.vline + ((int64_t)(J - 1) * k.n + (int64_t)I * k.rb) * P : nullptr;
+    r.above = I + 1 < k.ni;
+    r.right = J + 1 < k.nj;
+    return g;
+}
+
 }  // namespace sigk

@@ -109,7 +109,36 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
-enum { kModeGram = 0, kModeTable = 1 };
+enum { kModeGram = 0, kModeTable = 1, kModeLines = 2, kModeBlock = 3 };
+
+// Two-level (block) checkpointing of one long pair for its gradient.  The
+// grid of m x n cells is cut into blocks of rb rows (a multiple of 64) and cb
+// columns.  A first forward sweep over the whole pair (kModeLines) keeps the
+// edge series on the block boundaries: the top edges of the last row of every
+// block row but the top one (hline, [ni-1][m][P]) and the right edges of the
+// last column of every block column but the last one (vline, [nj-1][n][P]).
+// Then, block anti-diagonal by anti-diagonal from the top-right corner down,
+// each block is a small pair of its own (kModeBlock): its forward sweep is
+// recomputed from its bottom and left lines into per-slot checkpoints, and
+// its adjoint takes the cotangents of its top and right edges from the blocks
+// above and to its right (lam_h: one row of [m][P], shared down each block
+// column; lam_v: one column of [n][P], shared along each block row) and
+// leaves those of its bottom and left edges in the same places.
+struct BlockGeo {
+    int64_t m, n;       // cells of the pair
+    int rb, cb;         // rows (multiple of 64) and columns per block
+    int ni, nj;         // blocks along the rows (y) and the columns (x)
+    int kb;             // strips per block, rb / 64
+    int diag;           // block anti-diagonal I + J of a kModeBlock launch
+    int j_lo, nb;       // its first block column and number of blocks
+    double* hline;
+    double* vline;
+    int64_t slot_snap;  // doubles of frontier snapshots per block slot
+    int64_t slot_ckpt;  // doubles of wave-state checkpoints per block slot
+    int slot_prog;      // progress counters per slot (kb + 2: a sentinel on
+                        // either side, always complete)
+    int64_t y_gdx;      // first double of y's increment gradients in gdx
+};
 
 struct FwdArgs {
     int mode;
@@ -135,6 +164,7 @@ struct FwdArgs {
                          // [strips][delta_steps(m)][64] (gram mode)
     int64_t delta_pair;  // doubles per pair in delta
     int ckpt_every;    // steps between wave-state checkpoints (adjoint)
+    BlockGeo blk;      // kModeLines / kModeBlock
     long long watchdog_ticks;  // 100 MHz ticks before a wait is abandoned
 };
 
@@ -146,6 +176,7 @@ struct BwdArgs {
     double* snap;            // frontier snapshots written by the checkpoint pass
     double* ckpt;            // wave-state checkpoints + per-chunk depths
     double* lam_front;       // adjoint frontier (one row per pair, [m][P])
+    double* lam_v;           // kModeBlock: right/left edge cotangents, [n][P]
     int* lam_prog;           // adjoint progress counters (columns done from the right)
     double* gdx;             // [sum len][d]: dL/d(increment) at the increment's first point
     double* scratch;         // per workgroup: kCkptEvery x P x 64 recomputed bottom edges

@@ -305,8 +305,10 @@ __device__ __forceinline__ void lds_copy(double* dst, const double* src) {
 }
 
 // CH: columns per frontier chunk; RB: columns of the increment ring; SQ:
-// square truncation of the tile matrix (the paper's fixed-order tile).
-template <int P, int D, int CH, int RB, bool SQ = false>
+// square truncation of the tile matrix (the paper's fixed-order tile); BLK:
+// the boundary hooks of block checkpointing (left edges from a line, a bottom
+// line for strip 0, right-edge lines written during the sweep).
+template <int P, int D, int CH, int RB, bool SQ = false, bool BLK = false>
 struct StripCtx {
     const FwdArgs& a;
     Geo& g;
@@ -339,6 +341,13 @@ struct StripCtx {
     double* ck;         // wave-state checkpoints of this strip or null
     double* ckq;        // Neumann depth per chunk (with ck)
     int ck_every;
+    // block checkpointing (BLK): left edges of the strip's rows at column 0
+    // (null: the axis), whether strip 0 reads a bottom line through Fin, and
+    // the right-edge lines of the block columns (null: none written)
+    const double* left = nullptr;
+    bool below_line = false;
+    double* vl = nullptr;
+    int vcnt = 0;  // steps until the lane's column is the last of a block column
 
     __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH, RB>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
@@ -477,6 +486,20 @@ struct StripCtx {
         }
     }
 
+    // After the cell of column col (BLK, with vl): at the last column of a
+    // block column (except the grid's last) keep the cell's right edge.
+    __device__ __forceinline__ void vline_hook(int col, bool act) {
+        if (vl == nullptr) return;
+        if (vcnt == 0 && act && col + 1 < g.m) {
+            const int J = (col + 1) / a.blk.cb;
+            double* dst =
+                vl + ((int64_t)(J - 1) * a.blk.n + (int64_t)s * kWave + lane_id()) * P;
+#pragma unroll
+            for (int i = 0; i < P; ++i) dst[i] = B[i];
+        }
+        vcnt = vcnt == 0 ? a.blk.cb - 1 : vcnt - 1;
+    }
+
     // Cell coefficient c = <dx_col, dy_row> of step t into cn.  For small
     // orders it is computed one step ahead so that the LDS latency of the
     // increments overlaps the cell map (several waves share a SIMD there and
@@ -552,6 +575,7 @@ struct StripCtx {
                 B[i] = Bn[i];
                 Ac[i] = An[i];
             }
+            if constexpr (BLK) vline_hook(col, act);
             if (has_above && lane == kWave - 1 && act) {
                 double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
                 lds_copy<P>(dst, An);
@@ -561,8 +585,19 @@ struct StripCtx {
 #pragma unroll
         for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
         if (EDGE && col == 0) {
+            bool axis = true;
+            if constexpr (BLK) {
+                if (left != nullptr && lane_ok) {
+                    const double* lp = left + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
-            for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+                    for (int i = 0; i < P; ++i) B[i] = lp[i];
+                    axis = false;
+                }
+            }
+            if (axis) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
+            }
         }
         // small orders: coefficient computed one step ahead; large orders
         // (one wave per SIMD, registers scarce): computed here
@@ -586,6 +621,7 @@ struct StripCtx {
             B[i] = Bn[i];
             Ac[i] = An[i];
         }
+        if constexpr (BLK) vline_hook(col, act);
         if (has_above && lane == kWave - 1 && act) {
             double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
 #pragma unroll
@@ -663,9 +699,12 @@ struct StripCtx {
         const int row0 = s * kWave;
         nrows = min(kWave, g.n - row0);
         lane_ok = lane < nrows;
-        has_below = s > 0;
+        has_below = s > 0 || (BLK && below_line);
         has_above = row0 + kWave < g.n;
         nvalid = (unsigned)nrows;
+        if constexpr (BLK) {
+            if (vl != nullptr) vcnt = (a.blk.cb - 1 + lane) % a.blk.cb;
+        }
         R.init();
         const int l = row0 + lane;
         double n2 = 0.0;

@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
     for must in ("sigk_pair", "sigk_gram", "sigk_plan_ragged", "sigk_plan_run",
                  "sigk_plan_backward", "sigk_read_status"):
         assert must in names
-    assert len(names) == 27
+    assert len(names) == 30
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -287,6 +287,50 @@ def test_gram_workspace_rejections(lib):
     assert lib.sigk_gram_workspace_size(3, 3, 10, 10, 4, 0, ctypes.byref(o), None) == -1
 
 
+def long_size(lib, lx, ly, d, rows=0, cols=0, order=5):
+    b = ctypes.c_size_t()
+    o = _lib.make_opts(order=order)
+    rc = lib.sigk_pair_backward_workspace_size(lx, ly, d, rows, cols, ctypes.byref(o),
+                                               ctypes.byref(b))
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    rc2 = lib.sigk_pair_backward_blocks(lx, ly, d, rows, cols, ctypes.byref(o), ctypes.byref(r),
+                                        ctypes.byref(c))
+    assert rc == rc2
+    return rc, b.value, (r.value, c.value)
+
+
+def test_long_pair_backward_layout(lib):
+    """Block checkpointing of one long pair: block sizes, and a workspace that
+    holds the boundary lines, one anti-diagonal of block checkpoints and the
+    adjoint scratch, far below per-strip checkpoints of the whole grid."""
+    P, d = 5, 8
+    rc, nb, (rb, cb) = long_size(lib, 1_000_001, 1_000_001, d)
+    assert rc == 0 and rb % 64 == 0 and rb == cb
+    m = n = 1_000_000
+    ni, nj = -(-n // rb), -(-m // cb)
+    lines = ((ni - 1) * m + (nj - 1) * n) * P * 8
+    kb = rb // 64
+    states = (cb + 64 + 15) // 16 + 1
+    per_slot = kb * (cb * P + states * 2 * P * 64 + -(-(-(-cb // 32)) // 64) * 64) * 8
+    assert lines + min(ni, nj) * per_slot <= nb <= lines + min(ni, nj) * per_slot + (1 << 30)
+    assert nb < 60e9  # per-strip checkpoints of the 1e12 cells would take terabytes
+    # explicit blocks; short pairs clamp them; one-column blocks are valid
+    assert long_size(lib, 701, 501, 3, 128, 100)[2] == (128, 100)
+    assert long_size(lib, 10, 1000, 2, 0, 0)[2][1] == 9
+    assert long_size(lib, 300, 200, 3, 64, 1)[0] == 0
+    assert long_size(lib, 300, 200, 3, 1024, 0)[2][0] == 256  # rows clamped to whole strips
+    # degenerate pairs are valid (k = 1, no gradient)
+    for lx, ly in ((0, 5), (1, 1), (2, 0)):
+        assert long_size(lib, lx, ly, 2)[0] == 0
+    # rejections: rows not whole strips, negative sizes, d outside the adjoint's buckets
+    assert long_size(lib, 300, 200, 3, 100, 0)[0] == _lib.SIGK_EINVAL
+    assert long_size(lib, 300, 200, 3, -64, 0)[0] == _lib.SIGK_EINVAL
+    assert long_size(lib, -1, 200, 3)[0] == _lib.SIGK_EINVAL
+    assert long_size(lib, 300, 200, 0)[0] == _lib.SIGK_EINVAL
+    assert long_size(lib, 300, 200, 40)[0] == _lib.SIGK_EUNSUPPORTED
+    assert long_size(lib, 300, 200, 3, order=30)[0] == _lib.SIGK_EUNSUPPORTED
+
+
 # ---------------------------------------------------------------- validation before launch
 def test_compute_calls_validate_before_the_device(lib):
     o = _lib.make_opts(order=8)
@@ -313,6 +357,22 @@ def test_compute_calls_validate_before_the_device(lib):
     # a Gram call whose progress slots would not fit 32-bit indices
     assert lib.sigk_gram(FAKE_DEV, 40000, FAKE_DEV, 40000, 2, 1 << 20, 2, 0, ctypes.byref(o),
                          FAKE_DEV, ws, 1 << 62, None) == -1
+
+    # long-pair gradient: null pointers and a small workspace are rejected
+    one = ctypes.byref(o)
+    need = long_size(lib, 10, 12, 2, order=8)[1]
+    args = [FAKE_DEV, 10, FAKE_DEV, 12, 2, FAKE_DEV, 0, 0, one, None, FAKE_DEV, FAKE_DEV,
+            ws, need, None]
+    for i in (0, 2, 5, 10, 11, 12):
+        bad = list(args)
+        bad[i] = None
+        assert lib.sigk_pair_backward(*bad) == -1, i
+    small_ws = list(args)
+    small_ws[13] = need - 1
+    assert lib.sigk_pair_backward(*small_ws) == -2
+    bad_rows = list(args)
+    bad_rows[6] = 65
+    assert lib.sigk_pair_backward(*bad_rows) == -1
 
     rc, plan = make_plan(lib, [0, 100, 180], [[0, 1], [1, 1]], 3, order=8)
     assert rc == 0
