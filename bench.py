@@ -8,7 +8,9 @@ depth, wavefront propagation over the 999,999 x 999,999 grid, corner value.
 
 Also measured (field "workloads"): the 64 x 64 Gram (length 1024, d 16,
 sigma 1 and 4), the ragged batch of 512 pairs (graph replay, autotuned order),
-MMD^2 forward + backward (32 + 32 paths, length 2048, d 8) and the 8 x 8 Gram.
+MMD^2 forward + backward (32 + 32 paths, length 2048, d 8), the 8 x 8 Gram,
+runtime against d (length 4096) and forward + backward of the headline pair
+(block checkpointing).
 Every workload runs at the smallest compiled edge order whose run raises no
 truncation warning (the library's tail check), chosen before timing.
 
@@ -145,6 +147,8 @@ def extras(torch, sk, dev, only=""):
         mmd(torch, sk, dev, synth, res)
     if want("dim_sweep_len4096"):
         dim_sweep(torch, sk, dev, synth, frac, res)
+    if want("long_pair_1e6_d8_fwd_bwd"):
+        long_grad(torch, sk, dev, synth, res)
     return res
 
 
@@ -189,9 +193,27 @@ def ragged(torch, sk, dev, synth, tune, frac, res):
     g = plan.capture(pd, out)
     ms = timed(g.replay, torch)
     c = sk.counters(plan.ws)
+    uniform = {"cells_per_s": plan.cells / (ms / 1e3), "ms": ms, "order": tuned["order"],
+               "grid": tuned["grid"], "flops": c["flops"], "fp64_frac": frac(c["flops"], ms),
+               "status": c["status"]}
+    # per-pair orders: one launch per order class, all in one graph
+    orders, rungs = tune.tune_ragged_orders(pd, off, pairs, hint=FIRST_ORDER)
+    cp = sk.OrderClassPlan(off, pairs, pool.shape[1], orders, device=dev)
+    out2 = torch.empty(len(pairs), dtype=torch.float64, device=dev)
+    g2 = cp.capture(pd, out2)
+    ms2 = timed(g2.replay, torch)
+    c2 = cp.counters()
+    diff = (out2 - out).abs() / out.abs().clamp(min=1.0)
+    per_pair = {"cells_per_s": cp.cells / (ms2 / 1e3), "ms": ms2,
+                "classes": {str(k): v for k, v in sorted(cp.classes.items())}, "rungs": rungs,
+                "flops": c2["flops"], "fp64_frac": frac(c2["flops"], ms2),
+                "status": c2["status"], "max_rel_diff_vs_uniform": float(diff.max())}
     res["ragged512_len64to4096_d32_graph"] = {
-        "cells_per_s": plan.cells / (ms / 1e3), "ms": ms, "order": tuned["order"],
-        "grid": tuned["grid"], "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
+        "cells_per_s": per_pair["cells_per_s"], "ms": ms2, "policy": "per_pair",
+        "status": c2["status"] | c["status"], "per_pair": per_pair, "uniform": uniform,
+        "note": "per_pair: each pair at the smallest order whose own truncation estimate is "
+                "within budget, one persistent launch per order class in one HIP graph; "
+                "uniform: every pair at the smallest order with no warning for the batch"}
 
 
 def mmd(torch, sk, dev, synth, res):
@@ -235,6 +257,49 @@ def mmd(torch, sk, dev, synth, res):
         "note": "fwd+bwd: forward cells over the time of forward plus backward; status and "
                 "flops of the timed run (forward sweeps and adjoint sweep, counted on the "
                 "device)"}
+
+
+def long_grad(torch, sk, dev, synth, res):
+    """k(x, y) and its gradient for the long pair (1e6 points, d 8) by block
+    checkpointing, at the edge order the forward workload selects (its
+    ladder is re-run here, untimed).  One warm-up call on a short pair loads
+    the kernels; the workspace is allocated before the timed call."""
+    from paper_2502_20392_amd import _lib
+    x, y = synth.long_pair()
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    order = None
+    for p in [p for p in _lib.BWD_ORDERS if p >= FIRST_ORDER]:
+        sk.pair(xd, yd, order=p)
+        if not sk.counters()["status"] & _lib.WARN_TRUNC:
+            order = p
+            break
+    nb, blocks = sk.pair_backward_workspace_size(len(x), len(y), x.shape[1], order=order)
+    ws = sk.workspace(nb, dev)
+    sk.pair_backward(xd[:5000], yd[:4000], order=order, ws=ws)
+    gx = torch.zeros_like(xd)
+    gy = torch.zeros_like(yd)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    k, _, _ = sk.pair_backward(xd, yd, grad_x=gx, grad_y=gy, order=order, ws=ws)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    c = sk.counters(ws)
+    cells = (len(x) - 1) * (len(y) - 1)
+    res["long_pair_1e6_d8_fwd_bwd"] = {
+        "cells_per_s": cells / (ms / 1e3), "ms": ms, "order": order, "k": k.item(),
+        "status": c["status"], "trunc_est": c["trunc_est"], "workspace_bytes": nb,
+        "block": list(blocks), "fwd_cells": c["cells"], "bwd_cells": c["bwd_cells"],
+        "fwd_flops": c["flops"], "bwd_flops": c["bwd_flops"],
+        "fp64_frac": (c["flops"] + c["bwd_flops"]) / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+        "note": "one call: whole-pair sweep keeping block-boundary lines, then per block "
+                "anti-diagonal a checkpointing sweep and the adjoint; cells = the pair's "
+                "cells over the call's time; fwd_cells counts both forward sweeps"}
+    print(f"# long pair fwd+bwd: order {order} {ms / 1e3:.2f} s", file=sys.stderr, flush=True)
 
 
 def host_info():

@@ -195,6 +195,21 @@ uint64_t sigk_plan_cells(const sigk_plan* plan);
  */
 int sigk_plan_upload(const sigk_plan* plan, void* ws, size_t ws_bytes, void* stream);
 /*
+ * Output slots (host, before sigk_plan_upload): pair p writes
+ * out[out_index[p]] instead of out[p], and the plan's calls touch no other
+ * element of out, so several plans (for example one per edge order) can fill
+ * one output array.  out_index [npairs]: distinct values in
+ * [0, 2^30); SIGK_EINVAL otherwise.  out must then hold max(out_index) + 1
+ * doubles.  The adjoint's grad_out stays indexed by the plan's pair order.
+ */
+int sigk_plan_set_outputs(sigk_plan* plan, const int64_t* out_index);
+/*
+ * Byte offset in the plan's workspace of its per-pair truncation estimates
+ * (npairs doubles, the sum over each pair's cells described under tail_tol),
+ * valid once the stream has passed a forward call of the plan (host).
+ */
+size_t sigk_plan_estimates_offset(const sigk_plan* plan);
+/*
  * Evaluate the batch: out[p] = k(path pairs[p][0], path pairs[p][1]).
  * pool: [sum len][d] FP64 device.  One persistent launch preceded by a small
  * reset kernel, no host-device copies: capturable in a HIP graph.

@@ -2,7 +2,7 @@
 (arXiv 2502.20392).  The compute path is libsigk.so (hand-written HIP for
 gfx950) behind the C ABI of include/sigk.h; this package is its Python
 binding (PyTorch for device memory and streams) plus autograd wrappers."""
-from .api import (RaggedPlan, backward, counters, estimate_order, gram, gram_ragged,  # noqa: F401
-                  gram_static, last_autograd_counters, last_workspace, mmd2, order_bound, pair,
+from .api import (OrderClassPlan, RaggedPlan, backward, counters, estimate_order,  # noqa: F401
+                  gram, gram_ragged, gram_static, last_autograd_counters, last_workspace, mmd2, order_bound, pair,
                   pair_backward, pair_backward_workspace_size, ragged, sigkernel_gram, workspace)
 from . import _lib  # noqa: F401

@@ -80,6 +80,8 @@ SIGNATURES = {
     "sigk_plan_backward_workspace_size": (_SZ, [_P]),
     "sigk_plan_cells": (ctypes.c_uint64, [_P]),
     "sigk_plan_upload": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "sigk_plan_set_outputs": (ctypes.c_int, [_P, _P]),
+    "sigk_plan_estimates_offset": (_SZ, [_P]),
     "sigk_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_gram_ragged": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _P, _I64, _I64,
                                         ctypes.POINTER(Opts), _P, _P, _SZ, _P]),

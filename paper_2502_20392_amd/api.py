@@ -242,7 +242,9 @@ class RaggedPlan:
     """
 
     def __init__(self, offsets, pairs, d, order=12, tol=None, tail_tol=None, grid=0,
-                 fixed_depth=False, device="cuda", square=False):
+                 fixed_depth=False, device="cuda", square=False, out_index=None):
+        """out_index: optional host int64 [npairs] of distinct output slots (pair p
+        writes out[out_index[p]]; no other element of out is touched)."""
         lib = _lib.load()
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
@@ -255,6 +257,13 @@ class RaggedPlan:
                                         self.pairs.ctypes.data_as(ctypes.c_void_p), self.npairs,
                                         ctypes.byref(self.opts), ctypes.byref(h)))
         self._h = h
+        self.out_len = self.npairs
+        if out_index is not None:
+            oi = np.ascontiguousarray(out_index, dtype=np.int64).reshape(-1)
+            if oi.shape[0] != self.npairs:
+                raise ValueError("out_index must have one slot per pair")
+            _lib.check(lib.sigk_plan_set_outputs(h, oi.ctypes.data_as(ctypes.c_void_p)))
+            self.out_len = int(oi.max()) + 1 if oi.size else 0
         self.cells = int(lib.sigk_plan_cells(h))
         self.ws_bytes = int(lib.sigk_plan_workspace_size(h))
         self.bwd_ws_bytes = int(lib.sigk_plan_backward_workspace_size(h))
@@ -298,12 +307,20 @@ class RaggedPlan:
         pool = self._pool(pool)
         ws = self.ensure_workspace()
         if out is None:
-            out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
-        _check_buffer(out, "out", self.npairs, pool.device)
+            out = torch.empty(self.out_len, dtype=torch.float64, device=pool.device)
+        _check_buffer(out, "out", self.out_len, pool.device)
         _lib.check(_lib.load().sigk_plan_run(self._h, _ptr(pool), _ptr(out), _ptr(ws),
                                              ws.numel(), _stream()))
         _tls.ws = ws
         return out
+
+    def estimates(self):
+        """Per-pair truncation estimates of the last forward call (a view into the
+        workspace: [npairs] float64 on the device)."""
+        if self.ws is None:
+            raise RuntimeError("the plan has not run")
+        off = int(_lib.load().sigk_plan_estimates_offset(self._h))
+        return self.ws[off: off + 8 * self.npairs].view(torch.float64)
 
     def capture(self, pool, out):
         """Record ``run(pool, out)`` (reset kernel + persistent launch) into a HIP graph.
@@ -323,8 +340,8 @@ class RaggedPlan:
         pool = self._pool(pool)
         ws = self.ensure_workspace(backward=True)
         if out is None:
-            out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
-        _check_buffer(out, "out", self.npairs, pool.device)
+            out = torch.empty(self.out_len, dtype=torch.float64, device=pool.device)
+        _check_buffer(out, "out", self.out_len, pool.device)
         _lib.check(_lib.load().sigk_plan_run_checkpointed(self._h, _ptr(pool), _ptr(out),
                                                           _ptr(ws), ws.numel(), _stream()))
         _tls.ws = ws
@@ -345,6 +362,93 @@ class RaggedPlan:
                       _stream()))
         _tls.ws = ws
         return grad_pool
+
+
+class OrderClassPlan:
+    """A ragged batch whose pairs run at edge orders of their own: one
+    RaggedPlan per distinct order (a persistent launch each, in sequence on the
+    stream), every class writing its pairs' slots of one output array.
+
+    orders: host int [npairs], each pair's compiled edge order (for example
+    from ``tune.tune_ragged_orders``); grids: optional {order: grid}."""
+
+    def __init__(self, offsets, pairs, d, orders, tol=None, tail_tol=None, grids=None,
+                 device="cuda"):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        orders = np.asarray(orders).reshape(-1)
+        if orders.shape[0] != pairs.shape[0]:
+            raise ValueError("one order per pair")
+        self.npairs = pairs.shape[0]
+        self.plans = []
+        for p in sorted(set(int(o) for o in orders)):
+            idx = np.nonzero(orders == p)[0]
+            g = (grids or {}).get(p, 0)
+            self.plans.append(RaggedPlan(offsets, pairs[idx], d, order=p, tol=tol,
+                                         tail_tol=tail_tol, grid=g, device=device,
+                                         out_index=idx))
+        self.cells = sum(pl.cells for pl in self.plans)
+        self.classes = {pl.order: pl.npairs for pl in self.plans}
+        # launch order: the class with the longest dependency chain first (a
+        # pair's chain: its columns plus one start lag per strip, each step
+        # costing about P^2), so that the shorter classes fill in around it
+        offs = np.asarray(offsets, dtype=np.int64)
+        lens = np.diff(offs)
+
+        def chain(pl):
+            lx = lens[pl.pairs[:, 0]] - 1
+            ly = lens[pl.pairs[:, 1]] - 1
+            steps = lx + 96 * ((ly + 63) // 64)
+            return float(steps.max() if steps.size else 0) * pl.order ** 2
+        self.plans.sort(key=chain, reverse=True)
+        self._streams = None
+
+    def run(self, pool, out=None, concurrent=True):
+        """Every class's launch; with ``concurrent`` each on a side stream of its
+        own (forked from and joined back into the current stream, all at the
+        default priority), so that the classes overlap."""
+        if out is None:
+            out = torch.empty(self.npairs, dtype=torch.float64, device=pool.device)
+        _check_buffer(out, "out", self.npairs, pool.device)
+        if not concurrent or len(self.plans) == 1:
+            for pl in self.plans:
+                pl.run(pool, out)
+            return out
+        for pl in self.plans:  # workspaces and uploads before any fork
+            pl._pool(pool)
+            pl.ensure_workspace()
+        if self._streams is None:
+            self._streams = [torch.cuda.Stream(device=pool.device) for _ in self.plans]
+        main = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(main)
+        for pl, st in zip(self.plans, self._streams):
+            st.wait_event(fork)
+            with torch.cuda.stream(st):
+                pl.run(pool, out)
+            join = torch.cuda.Event()
+            join.record(st)
+            main.wait_event(join)
+        return out
+
+    def capture(self, pool, out):
+        """Record every class's run into one HIP graph (after an eager run)."""
+        self.run(pool, out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(pool, out)
+        return g
+
+    def counters(self):
+        """Cells, flops and status summed (OR-ed) over the classes' last runs."""
+        tot = {"cells": 0, "flops": 0, "status": 0, "trunc_est": 0.0}
+        for pl in self.plans:
+            c = counters(pl.ws)
+            tot["cells"] += c["cells"]
+            tot["flops"] += c["flops"]
+            tot["status"] |= c["status"]
+            tot["trunc_est"] = max(tot["trunc_est"], c["trunc_est"])
+        return tot
 
 
 def ragged(pool, offsets, pairs, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False,

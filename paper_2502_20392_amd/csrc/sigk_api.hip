@@ -286,6 +286,8 @@ struct sigk_plan {
     int64_t max_len = 0, M = 0, S_max = 0, nbk_f = 0, nbk_b = 0;
     int lag_f = 0, lag_b = 0;
     size_t o_hist = 0, o_histr = 0;
+    // output slots set by sigk_plan_set_outputs (default: out[p] for pair p)
+    bool custom_out = false;
 };
 
 namespace {
@@ -330,12 +332,28 @@ void plan_layout(sigk_plan& p) {
 
 bool valid_opts(const sigk_opts* o) { return o == nullptr || (std::isfinite(o->tol) && std::isfinite(o->tail_tol)); }
 
+// k = 1 in the output slot of every pair without cells (plans whose pairs
+// write chosen slots of a shared output: the other slots are not touched).
+__global__ void unit_out_kernel(const PairDesc* desc, int64_t npairs, double* out) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t p = i0; p < npairs; p += (int64_t)gridDim.x * blockDim.x)
+        if (desc[p].lx < 2 || desc[p].ly < 2) out[desc[p].out_idx] = 1.0;
+}
+
 // Reset of a plan's workspace before a forward sweep: header, progress flags,
 // truncation estimates and the outputs (k = 1 where a pair has no cells).
 hipError_t plan_reset(const sigk_plan* plan, double* out, char* base, hipStream_t s) {
-    return launch_reset((WsHeader*)base, (int*)(base + plan->o_prog), plan->nprog, out,
-                        out ? plan->npairs : 0, (double*)(base + plan->o_est), plan->npairs,
-                        (unsigned)plan->P, s);
+    hipError_t e = launch_reset((WsHeader*)base, (int*)(base + plan->o_prog), plan->nprog, out,
+                                out && !plan->custom_out ? plan->npairs : 0,
+                                (double*)(base + plan->o_est), plan->npairs, (unsigned)plan->P,
+                                s);
+    if (e == hipSuccess && out && plan->custom_out && plan->npairs > 0) {
+        const int blocks = (int)std::min<int64_t>((plan->npairs + 255) / 256, 1024);
+        hipLaunchKernelGGL(unit_out_kernel, dim3(blocks), dim3(256), 0, s,
+                           (const PairDesc*)(base + plan->o_desc), plan->npairs, out);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 // The forward sweep of a plan (after plan_reset): one persistent launch, then
@@ -644,6 +662,23 @@ int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((
 }  // namespace
 
 void sigk_plan_destroy(sigk_plan* plan) { delete plan; }
+
+int sigk_plan_set_outputs(sigk_plan* plan, const int64_t* out_index) {
+    if (!plan || (plan->npairs > 0 && !out_index) || plan->dev_tables) return SIGK_EINVAL;
+    std::vector<int64_t> sorted(out_index, out_index + plan->npairs);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t i = 0; i < sorted.size(); ++i)
+        if (sorted[i] < 0 || sorted[i] > INT32_MAX / 2 || (i > 0 && sorted[i] == sorted[i - 1]))
+            return SIGK_EINVAL;
+    for (int64_t p = 0; p < plan->npairs; ++p) {
+        plan->desc[(size_t)p].out_idx = (int32_t)out_index[p];
+        plan->desc[(size_t)p].out_idx2 = -1;
+    }
+    plan->custom_out = true;
+    return SIGK_OK;
+}
+
+size_t sigk_plan_estimates_offset(const sigk_plan* plan) { return plan ? plan->o_est : 0; }
 
 size_t sigk_plan_workspace_size(const sigk_plan* plan) { return plan ? plan->fwd_total : 0; }
 size_t sigk_plan_backward_workspace_size(const sigk_plan* plan) {

@@ -109,6 +109,33 @@ def tune_ragged(pool, offsets, pairs, hint=6, reps=2, tol=None, use_cache=True):
     return best
 
 
+def tune_ragged_orders(pool, offsets, pairs, hint=4, tol=None, tail_tol=None):
+    """Each pair's edge order: the smallest compiled order from `hint` up whose
+    forward sweep keeps the pair's own truncation estimate within the budget
+    (tail_tol, default 2^-36).  The pairs still above it after a rung are run
+    again, alone, at the next one.  Returns (orders [npairs], rungs), rungs =
+    [{"order", "pairs", "passed"}] (synchronises)."""
+    d = pool.shape[1]
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    budget = tail_tol if tail_tol else 2.0 ** -36
+    ladder = [p for p in _lib.ORDERS if p >= hint] or [_lib.ORDERS[-1]]
+    orders = np.full(pairs.shape[0], ladder[-1], dtype=np.int64)
+    todo = np.arange(pairs.shape[0])
+    rungs = []
+    for p in ladder:
+        if todo.size == 0:
+            break
+        plan = RaggedPlan(offsets, pairs[todo], d, order=p, tol=tol, tail_tol=tail_tol,
+                          device=pool.device)
+        plan.run(pool)
+        est = plan.estimates().cpu().numpy()
+        ok = np.isfinite(est) & (est <= budget)
+        orders[todo[ok]] = p
+        rungs.append({"order": p, "pairs": int(todo.size), "passed": int(ok.sum())})
+        todo = todo[~ok]
+    return orders, rungs
+
+
 def tune_pair(x, y, hint=5, reps=1, tol=None, use_cache=True):
     """Tune one pair evaluation.  Returns {"order", "grid", "ms", "status"}."""
     key = "pair:" + _digest(x, y) + f":{hint}:{tol}"

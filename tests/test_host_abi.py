@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
     for must in ("sigk_pair", "sigk_gram", "sigk_plan_ragged", "sigk_plan_run",
                  "sigk_plan_backward", "sigk_read_status"):
         assert must in names
-    assert len(names) == 30
+    assert len(names) == 32
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -212,6 +212,29 @@ def test_plan_rejections(lib, case, code):
     rc, plan = make_plan(lib, offsets, pairs, d, order)
     assert rc == code
     assert not plan.value  # no plan is returned on failure
+
+
+def test_plan_output_slots(lib):
+    """sigk_plan_set_outputs: distinct slots in [0, 2^30) are accepted; duplicate,
+    negative or too large slots and a null array are refused; the estimates'
+    offset lies inside the forward workspace."""
+    rc, plan = make_plan(lib, [0, 100, 180, 200], [[0, 1], [1, 2], [2, 2]], 3)
+    assert rc == 0
+    try:
+        def set_(slots):
+            a = np.ascontiguousarray(slots, dtype=np.int64)
+            return lib.sigk_plan_set_outputs(plan, a.ctypes.data)
+        assert set_([0, 0, 1]) == -1
+        assert set_([0, -1, 2]) == -1
+        assert set_([0, 1, 1 << 30]) == -1
+        assert lib.sigk_plan_set_outputs(plan, None) == -1
+        assert set_([5, 1, (1 << 30) - 1]) == 0
+        off = lib.sigk_plan_estimates_offset(plan)
+        assert 0 < off and off + 3 * 8 <= lib.sigk_plan_workspace_size(plan)
+    finally:
+        lib.sigk_plan_destroy(plan)
+    assert lib.sigk_plan_set_outputs(None, None) == -1
+    assert lib.sigk_plan_estimates_offset(None) == 0
 
 
 def test_plan_null_arguments(lib):
