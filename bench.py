@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 FIRST_ORDER = 4  # every order search starts at the smallest compiled order
+MMD_CKPT_BUDGET = 8 << 30  # adjoint workspace allowed at once in the bounded MMD^2 run
 METRIC = "Goursat grid cells/s (fwd, fwd+bwd) at rel err ≤1e-10 vs FP64 oracle"
 
 
@@ -240,7 +241,10 @@ def mmd(torch, sk, dev, synth, res):
         Xt.grad = None
         sk.mmd2(Xt, Yt, order=order, check=True).backward()
 
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
     ms = timed(fb, torch, steps=2)
+    peak = torch.cuda.max_memory_allocated()
     tally = sk.last_autograd_counters()
     nx, lx = Xm.shape[0], Xm.shape[1]
     ny, ly = Ym.shape[0], Ym.shape[1]
@@ -254,9 +258,29 @@ def mmd(torch, sk, dev, synth, res):
         "fwd_cells": fwd_cells, "bwd_cells": bwd_cells,
         "fwd_flops": tally["flops"], "bwd_flops": tally["bwd_flops"],
         "fp64_frac": (tally["flops"] + tally["bwd_flops"]) / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+        "peak_mem_bytes": peak,
         "note": "fwd+bwd: forward cells over the time of forward plus backward; status and "
                 "flops of the timed run (forward sweeps and adjoint sweep, counted on the "
-                "device)"}
+                "device); peak_mem_bytes: torch's peak device allocation (checkpoints of "
+                "every pair with a gradient kept from the forward)"}
+
+    # the same with the checkpoints bounded: adjoint in groups of pairs
+    budget = MMD_CKPT_BUDGET
+
+    def fb_budget():
+        Xt.grad = None
+        sk.mmd2(Xt, Yt, order=order, check=True, ckpt_budget=budget).backward()
+
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    ms_b = timed(fb_budget, torch, steps=2)
+    peak_b = torch.cuda.max_memory_allocated()
+    tb = sk.last_autograd_counters()
+    res["mmd_32x32_len2048_d8_fwd_bwd"]["ckpt_budget"] = {
+        "budget_bytes": budget, "ms": ms_b, "cells_per_s": fwd_cells / (ms_b / 1e3),
+        "peak_mem_bytes": peak_b, "status": tb["status"],
+        "fp64_frac": (tb["flops"] + tb["bwd_flops"]) / (ms_b / 1e3) / 1e12 / FP64_PEAK_TFLOPS}
 
 
 def long_grad(torch, sk, dev, synth, res):

@@ -654,18 +654,89 @@ def _pool_and_pairs(X, Y, symmetric):
     return pool.contiguous(), offsets, pairs
 
 
+class _AdjointPairs:
+    """The pairs of an autograd call that need a gradient.  Without a budget
+    (or when every checkpoint fits it) one plan: its checkpointing forward
+    sweep gives the values and keeps the checkpoints for the adjoint.  With a
+    budget smaller than that plan's adjoint workspace, the pairs are split
+    into groups whose workspaces fit it: the forward is the plain sweep of all
+    pairs, and the backward runs each group's checkpointing sweep and adjoint
+    in turn, releasing its workspace before the next (one more forward sweep
+    of those pairs, checkpoint memory bounded by the budget)."""
+
+    def __init__(self, offsets, pairs, d, order, tol, device, budget=None):
+        self.offsets, self.pairs, self.d = offsets, pairs, d
+        self.order, self.tol, self.device = order, tol, device
+        self.plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=device)
+        self.groups = None
+        if budget is not None and self.plan.bwd_ws_bytes > budget:
+            n = len(pairs)
+            ng = max(2, -(-self.plan.bwd_ws_bytes // int(budget)))
+            while True:
+                parts = [g for g in np.array_split(np.arange(n), ng) if g.size]
+                sizes = [RaggedPlan(offsets, pairs[g], d, order=order, tol=tol,
+                                    device=device).bwd_ws_bytes for g in parts]
+                if max(sizes) <= budget or ng >= n:
+                    break
+                ng *= 2
+            self.groups = parts
+        self.peak_ws = (self.plan.bwd_ws_bytes if self.groups is None
+                        else max(sizes + [self.plan.ws_bytes]))
+
+    def forward(self, pool):
+        if self.groups is None:
+            return self.plan.run_checkpointed(pool)
+        return self.plan.run(pool)
+
+    def backward(self, pool, w, tally=None):
+        """The gradient of sum_p w[p] k_p with respect to the pool.  Releases the
+        checkpoints afterwards (the adjoint is run once per autograd call)."""
+        if self.groups is None:
+            g = self.plan.backward(pool, w, checkpointed=True)
+            if tally is not None:
+                tally.add(self.plan.ws, backward=True)
+            self._release(self.plan)
+            return g
+        self._release(self.plan)  # the forward's workspace is not needed any more
+        gpool = torch.zeros_like(pool)
+        for idx in self.groups:
+            gp = RaggedPlan(self.offsets, self.pairs[idx], self.d, order=self.order, tol=self.tol,
+                            device=self.device)
+            wi = w[torch.from_numpy(idx).to(w.device)].contiguous()
+            gp.backward(pool, wi, grad_pool=gpool)
+            if tally is not None:
+                tally.add(gp.ws, backward=True)
+            self._release(gp)
+        return gpool
+
+    @staticmethod
+    def _release(plan):
+        # drop every reference to the plan's workspace (the thread-local
+        # "last workspace" included), so its memory returns to the allocator
+        if getattr(_tls, "ws", None) is plan.ws:
+            _tls.ws = None
+        plan.ws = None
+
+
 class _GramFunction(torch.autograd.Function):
     """G = [k(X_i, Y_j)] with the adjoint sweep as backward."""
 
     @staticmethod
-    def forward(ctx, X, Y, order, tol, symmetric, check):
+    def forward(ctx, X, Y, order, tol, symmetric, check, ckpt_budget):
         pool, offsets, pairs = _pool_and_pairs(X, Y, symmetric)
-        plan = RaggedPlan(offsets, pairs, X.shape[2], order=order, tol=tol, device=X.device)
         grad = X.requires_grad or (Y is not None and Y.requires_grad)
-        # with a gradient ahead, the checkpointing sweep gives the values and
-        # the checkpoints the adjoint needs (no second forward in backward)
-        vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
-        ctx.checkpointed = grad
+        if grad:
+            # with a gradient ahead, the checkpointing sweep gives the values and
+            # the checkpoints the adjoint needs (no second forward in backward),
+            # unless they exceed ckpt_budget
+            adj = _AdjointPairs(offsets, pairs, X.shape[2], order, tol, X.device, ckpt_budget)
+            plan = adj.plan
+            vals = adj.forward(pool)
+        else:
+            adj = None
+            plan = RaggedPlan(offsets, pairs, X.shape[2], order=order, tol=tol, device=X.device)
+            vals = plan.run(pool)
+        ctx.adj = adj
         ctx.check = check
         if check:
             ctx.tally = _tls.tally = _Tally()
@@ -680,7 +751,7 @@ class _GramFunction(torch.autograd.Function):
             G[jj, ii] = vals
         else:
             G.view(-1).copy_(vals)
-        ctx.plan, ctx.pool, ctx.pairs, ctx.symmetric = plan, pool, pairs, symmetric
+        ctx.pool, ctx.pairs, ctx.symmetric = pool, pairs, symmetric
         ctx.shapes = (X.shape, None if symmetric else Y.shape)
         return G
 
@@ -695,28 +766,29 @@ class _GramFunction(torch.autograd.Function):
             w = torch.where(ii == jj, gG[ii, jj], w)
         else:
             w = gG.reshape(-1)
-        gpool = ctx.plan.backward(ctx.pool, w.contiguous(), checkpointed=ctx.checkpointed)
+        gpool = ctx.adj.backward(ctx.pool, w.contiguous(), ctx.tally if ctx.check else None)
         if ctx.check:
-            ctx.tally.add(ctx.plan.ws, backward=True)
             _check_status(ctx.tally.status, "Gram backward")
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gX = gpool[:nxp].reshape(xs)
         gY = None if ctx.symmetric else gpool[nxp:].reshape(ys)
-        return gX, gY, None, None, None, None
+        return gX, gY, None, None, None, None, None
 
 
-def sigkernel_gram(X, Y=None, order=12, tol=None, check=False):
+def sigkernel_gram(X, Y=None, order=12, tol=None, check=False, ckpt_budget=None):
     """Differentiable Gram matrix of signature kernels (FP64, GPU).
 
     check: after the forward and the backward launches, read the device status
     (synchronises): raise on a watchdog trip or a non-finite value, warn on a
-    truncation warning; the counters are kept for ``last_autograd_counters``."""
+    truncation warning; the counters are kept for ``last_autograd_counters``.
+    ckpt_budget: bytes of adjoint workspace allowed at once (None: all
+    checkpoints kept from the forward; see _AdjointPairs)."""
     X = _check_paths(X, "X", 3)
     if Y is None:
-        return _GramFunction.apply(X, None, order, tol, True, check)
+        return _GramFunction.apply(X, None, order, tol, True, check, ckpt_budget)
     Y = _check_paths(Y, "Y", 3)
-    return _GramFunction.apply(X, Y, order, tol, False, check)
+    return _GramFunction.apply(X, Y, order, tol, False, check, ckpt_budget)
 
 
 class _MMD2Function(torch.autograd.Function):
@@ -728,7 +800,7 @@ class _MMD2Function(torch.autograd.Function):
     runs in a plain forward launch."""
 
     @staticmethod
-    def forward(ctx, X, Y, order, tol, check):
+    def forward(ctx, X, Y, order, tol, check, ckpt_budget):
         nx, lx, d = X.shape
         ny, ly, _ = Y.shape
         pool = torch.cat([X.reshape(-1, d), Y.reshape(-1, d)], dim=0).contiguous()
@@ -745,7 +817,7 @@ class _MMD2Function(torch.autograd.Function):
         need_x, need_y = X.requires_grad, Y.requires_grad
         use = [need_x, need_y, need_x or need_y]  # XX, YY, XY blocks with a gradient
         total = torch.zeros((), dtype=torch.float64, device=X.device)
-        plan_g = None
+        adj = None
         tally = _Tally() if check else None
         for grad in (True, False):
             sel = [u == grad for u in use]
@@ -753,16 +825,21 @@ class _MMD2Function(torch.autograd.Function):
                 continue
             pairs = np.concatenate([b for b, u in zip(blocks, sel) if u]).astype(np.int32)
             w = np.concatenate([x for x, u in zip(weights, sel) if u])
-            plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
-            vals = plan.run_checkpointed(pool) if grad else plan.run(pool)
+            if grad:
+                adj = _AdjointPairs(offsets, pairs, d, order, tol, X.device, ckpt_budget)
+                plan = adj.plan
+                vals = adj.forward(pool)
+            else:
+                plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, device=X.device)
+                vals = plan.run(pool)
             if tally is not None:
                 tally.add(plan.ws)
             wt = torch.from_numpy(w).to(X.device)
             total = total + (vals * wt).sum()
             if grad:
-                plan_g, w_g = plan, wt
-        ctx.plan = plan_g
-        ctx.w = w_g if plan_g is not None else None
+                w_g = wt
+        ctx.adj = adj
+        ctx.w = w_g if adj is not None else None
         ctx.tally = tally
         if tally is not None:
             _tls.tally = tally
@@ -773,22 +850,22 @@ class _MMD2Function(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         need_x, need_y = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        if ctx.plan is None or not (need_x or need_y):
-            return None, None, None, None, None
-        gpool = ctx.plan.backward(ctx.pool, (ctx.w * g).contiguous(), checkpointed=True)
+        if ctx.adj is None or not (need_x or need_y):
+            return None, None, None, None, None, None
+        gpool = ctx.adj.backward(ctx.pool, (ctx.w * g).contiguous(), ctx.tally)
         if ctx.tally is not None:
-            ctx.tally.add(ctx.plan.ws, backward=True)
             _check_status(ctx.tally.status, "MMD^2 backward")
         xs, ys = ctx.shapes
         nxp = xs[0] * xs[1]
         gx = gpool[:nxp].reshape(xs) if need_x else None
         gy = gpool[nxp:].reshape(ys) if need_y else None
-        return gx, gy, None, None, None
+        return gx, gy, None, None, None, None
 
 
-def mmd2(X, Y, order=12, tol=None, check=False):
+def mmd2(X, Y, order=12, tol=None, check=False, ckpt_budget=None):
     """Differentiable biased MMD^2 between path sets X [nx, lx, d] and Y [ny, ly, d].
 
-    check: as for ``sigkernel_gram`` (status read after forward and backward)."""
+    check: as for ``sigkernel_gram`` (status read after forward and backward).
+    ckpt_budget: as for ``sigkernel_gram``."""
     return _MMD2Function.apply(_check_paths(X, "X", 3), _check_paths(Y, "Y", 3), order, tol,
-                               check)
+                               check, ckpt_budget)

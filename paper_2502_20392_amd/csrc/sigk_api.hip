@@ -294,6 +294,16 @@ namespace {
 
 constexpr int kBwdMaxGrid = 2048;
 
+// Workgroups the adjoint's recompute scratch is sized for: those of the
+// adjoint launch on the current device (no more than `tickets`), or
+// kBwdMaxGrid where no device can be queried (workspace sizes asked for on a
+// host without one).  The launch never exceeds it.
+int bwd_scratch_grid(int P, int D, int64_t tickets) {
+    const int g = device_wgs(P, D, kKernelBwd);
+    const int64_t n = g > 0 ? std::min(g, kBwdMaxGrid) : kBwdMaxGrid;
+    return (int)std::max<int64_t>(std::min<int64_t>(n, tickets), 1);
+}
+
 void plan_layout(sigk_plan& p) {
     size_t o = align256(sizeof(WsHeader));
     p.o_desc = o;
@@ -325,8 +335,8 @@ void plan_layout(sigk_plan& p) {
     p.o_gdx = o;
     o = align256(o + sizeof(double) * (size_t)std::max<int64_t>(p.pool_points * p.d, 1));
     p.o_scr = o;
-    p.bwd_grid = kBwdMaxGrid;
-    o = align256(o + sizeof(double) * (size_t)p.bwd_grid * kCkptEvery * p.P * kWave);
+    p.bwd_grid = bwd_scratch_grid(p.P, p.D, p.ntk);
+    o = align256(o + sizeof(double) * (size_t)p.bwd_grid * 2 * kCkptEvery * p.P * kWave);
     p.bwd_total = o;
 }
 
@@ -1149,7 +1159,7 @@ namespace {
 struct LongLayout {
     int P = 0, D = 0;
     int64_t lx = 0, ly = 0, d = 0, m = 0, n = 0;
-    int rb = 0, cb = 0, ni = 0, nj = 0, kb = 0, nslots = 0, S = 0;
+    int rb = 0, cb = 0, ni = 0, nj = 0, kb = 0, nslots = 0, S = 0, bwd_grid = 0;
     int64_t slot_snap = 0, slot_ckpt = 0;
     int slot_prog = 0;
     size_t o_est = 0, o_prog = 0, o_front = 0, o_hline = 0, o_vline = 0, o_snap = 0, o_ckpt = 0,
@@ -1213,7 +1223,8 @@ int long_layout(int64_t lx, int64_t ly, int64_t d, int64_t brows, int64_t bcols,
     take(L.o_lamh, sizeof(double) * (size_t)(m * P));
     take(L.o_lamv, sizeof(double) * (size_t)(n * P));
     take(L.o_gdx, sizeof(double) * (size_t)((lx + ly) * d));
-    take(L.o_scr, sizeof(double) * (size_t)kBwdMaxGrid * kCkptEvery * P * kWave);
+    L.bwd_grid = bwd_scratch_grid(P, L.D, (int64_t)L.nslots * L.kb);
+    take(L.o_scr, sizeof(double) * (size_t)L.bwd_grid * 2 * kCkptEvery * P * kWave);
     L.total = o;
     return SIGK_OK;
 }
@@ -1328,7 +1339,7 @@ int sigk_pair_backward(const double* x, int64_t lx, const double* y, int64_t ly,
     k.slot_prog = L.slot_prog;
     k.y_gdx = lx * d;
     const int cgrid = std::max(device_wgs(L.P, L.D, kKernelCkpt), 1);
-    const int bgrid = std::min(std::max(device_wgs(L.P, L.D, kKernelBwd), 1), kBwdMaxGrid);
+    const int bgrid = L.bwd_grid;
 
     // 1. the whole pair once: k(x, y), its truncation estimate and the lines
     a.mode = kModeLines;

@@ -257,6 +257,7 @@ struct StripBwd {
         __syncthreads();
     }
 
+    // depth record of the chunk of step t: depth + kRoughFlag if rough
     __device__ __forceinline__ int depth_at(int t) const {
         const int CKCH = ckpt_chunk<P, D>;
         const int k = min(t, m - 1) / CKCH;
@@ -269,21 +270,23 @@ struct StripBwd {
 
     // Depth dispatch: one specialised segment loop per Neumann depth.
     template <int Q>
-    __device__ __forceinline__ void segment_at_depth(int q, int t0, int t1) {
+    __device__ __forceinline__ void segment_at_depth(int q, bool rough, int t0, int t1) {
         if constexpr (Q < P - 1) {
             if (q > Q) {
-                segment_at_depth<Q + 1>(q, t0, t1);
+                segment_at_depth<Q + 1>(q, rough, t0, t1);
                 return;
             }
         }
-        segment<Q>(q, t0, t1);
+        segment<Q>(q, rough, t0, t1);
     }
 
     // One segment [t0, t1) of kCkptEvery steps: recompute it forward from its
     // checkpoint, storing each step's bottom edges, then run the adjoint steps
     // last to first.  Q >= 0: depth fixed at compile time (== q); Q < 0: q.
+    // rough: the left edges are stored too (second half of the scratch) and
+    // read back instead of recovered from the right edges.
     template <int Q>
-    __device__ void segment(int q, int t0, int t1) {
+    __device__ void segment(int q, bool rough, int t0, int t1) {
         const int lane = lane_id();
         const int CH = ACH;
         const int W = kCkptEvery;
@@ -315,6 +318,11 @@ struct StripBwd {
             double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
 #pragma unroll
             for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+            if (rough) {
+                double* bdst = dst + kCkptEvery * P * kWave;
+#pragma unroll
+                for (int i = 0; i < P; ++i) bdst[i * kWave + lane] = B[i];
+            }
             const int ri = ring_slot_of<ARB>(col);
             double c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -349,6 +357,11 @@ struct StripBwd {
             double A[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = src[i * kWave + lane];
+            if (rough) {
+                const double* bsrc = src + kCkptEvery * P * kWave;
+#pragma unroll
+                for (int i = 0; i < P; ++i) B[i] = bsrc[i * kWave + lane];
+            }
             const int ri = ring_slot_of<ARB>(col);
             double dxv[D];
             double c0 = 0.0, c1 = 0.0;
@@ -393,12 +406,13 @@ struct StripBwd {
             // column 0 on a left line: the left edge is recovered like any
             // other (it is the right edge of the block to the left)
             const bool axis = col == 0 && left == nullptr;
+            const bool recover = !rough && col < m;  // rough: B is the stored left edge
             double lA[P], lB[P];
             double gc;
             if constexpr (Q >= 0)
-                gc = cell_adjoint_fixed<P, Q>(A, B, c, axis, col < m, lAo, lBst, lA, lB, R);
+                gc = cell_adjoint_fixed<P, Q>(A, B, c, axis, recover, lAo, lBst, lA, lB, R);
             else
-                gc = cell_adjoint<P>(A, B, c, q, axis, col < m, lAo, lBst, lA, lB, R);
+                gc = cell_adjoint<P>(A, B, c, q, axis, recover, lAo, lBst, lA, lB, R);
             if (!act) gc = 0.0;
             if (left_out && act && col == 0) {
                 double* lp = lamv + ((int64_t)s * kWave + lane) * P;
@@ -464,14 +478,16 @@ struct StripBwd {
         topl = has_above ? kWave - 1 : nrows - 1;
         for (int t0 = ((T - 1) / W) * W; t0 >= 0; t0 -= W) {
             const int t1 = min(t0 + W, T);
-            const int q = depth_at(t0);
+            const int rec = depth_at(t0);
+            const int q = rec % kRoughFlag;
+            const bool rough = rec >= kRoughFlag;
             load_dx_down_to(max(t0 - (kWave - 1), 0));
             if (has_above && !load_lin_down_to(max(t0 - (kWave - 1), 0))) return false;
             if (t0 < m && t0 / CH != bin_chunk) load_bin(t0 / CH);
             if constexpr (P <= 12)
-                segment_at_depth<0>(q, t0, t1);
+                segment_at_depth<0>(q, rough, t0, t1);
             else
-                segment<-1>(q, t0, t1);
+                segment<-1>(q, rough, t0, t1);
             if (t0 < m && (t0 % CH) == 0) flush_cols(t0, min(t0 + CH, m));
         }
         // dL/d(dy_l) of this lane's row
@@ -491,7 +507,7 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
     __shared__ LdsBwd<P, D> L;
     const FwdArgs& a = b.f;
     const int lane = lane_id();
-    double* scratch = b.scratch + (int64_t)blockIdx.x * (kCkptEvery * P * kWave);
+    double* scratch = b.scratch + (int64_t)blockIdx.x * (2 * kCkptEvery * P * kWave);
     unsigned long long cells = 0, flops = 0;
     for (;;) {
         unsigned t = 0;

@@ -80,6 +80,11 @@ static_assert(sizeof(PairDesc) == 64, "descriptor size");
 // ckpt_states(m) states of 2P x 64 doubles followed by the Neumann depth of
 // every frontier chunk (stored as doubles, padded to 64).
 constexpr int kCkptEvery = 16;
+// Per-chunk depth record of the checkpointing sweep: the depth plus
+// kRoughFlag where the chunk's bound of |c|^2 exceeds kRoughC2 (the adjoint
+// then keeps left edges in its scratch instead of recovering them).
+constexpr int kRoughFlag = 64;
+constexpr double kRoughC2 = 0.25;
 __host__ __device__ constexpr int64_t ckpt_states(int64_t m) {
     return (m + kWave + kCkptEvery - 1) / kCkptEvery + 1;
 }
@@ -179,7 +184,8 @@ struct BwdArgs {
     double* lam_v;           // kModeBlock: right/left edge cotangents, [n][P]
     int* lam_prog;           // adjoint progress counters (columns done from the right)
     double* gdx;             // [sum len][d]: dL/d(increment) at the increment's first point
-    double* scratch;         // per workgroup: kCkptEvery x P x 64 recomputed bottom edges
+    double* scratch;         // per workgroup: kCkptEvery x P x 64 recomputed bottom edges,
+                             // then as many left edges (rough segments)
 };
 
 // Records the HIP error string for sigk_strerror and returns SIGK_EDEVICE.

@@ -385,13 +385,19 @@ struct StripCtx {
         return true;
     }
 
-    // Depth of the chunk from the bound of |c|^2 over its cells.
+    // Depth of the chunk from the bound of |c|^2 over its cells.  With
+    // checkpoints, the depth is stored for the adjoint together with a flag
+    // (+kRoughFlag) where the bound allows |c| > 1/2: there the adjoint keeps
+    // each cell's left edge instead of recovering it from the right edge (the
+    // recovery inverts a triangular Toeplitz factor of norm up to e^|c| per
+    // step and loses precision over a segment for |c| of order 1 and above).
     __device__ __forceinline__ void set_depth(int c0, double cmax2) {
         int qq = 0;
 #pragma unroll
         for (int n = 1; n < P; ++n) qq = cmax2 > a.tau2[n] ? n : qq;
         q = uniform(qq);
-        if (ckq && lane_id() == 0) ckq[c0 / CH] = (double)q;
+        if (ckq && lane_id() == 0)
+            ckq[c0 / CH] = (double)(q + (cmax2 > kRoughC2 ? kRoughFlag : 0));
     }
 
     // D = 0: the coefficients of steps [c0, c0+CH) from the precomputed field

@@ -187,6 +187,60 @@ def test_mmd_reduced_vs_oracle(dev):
     assert np.abs(Xt.grad.cpu().numpy() - ref).max() <= 1e-10 * max(1, np.abs(ref).max())
 
 
+def test_checkpoint_budget_groups(dev):
+    """A checkpoint budget below the whole batch's adjoint workspace: the forward
+    runs plainly and the backward in groups of pairs, each with its own
+    checkpointing sweep and adjoint.  Same loss, gradients equal to the
+    unbudgeted ones to rounding (their sums run in another order), and the
+    oracle's MMD^2 gradient."""
+    X, Y = synth.mmd_sets(n=4, length=256)
+    Xt = T(X, dev).requires_grad_(True)
+    Yt = T(Y, dev).requires_grad_(True)
+    m0 = sk().mmd2(Xt, Yt, order=10)
+    m0.backward()
+    gx0, gy0 = Xt.grad.clone(), Yt.grad.clone()
+    offsets, pairs, d = _mmd_pairs(X, Y)
+    full = sk().api._AdjointPairs(offsets, pairs, d, 10, None, dev, None).plan.bwd_ws_bytes
+    # the workspace of one pair: its share plus the parts every plan has
+    one = sk().api._AdjointPairs(offsets, pairs[:1], d, 10, None, dev, None).plan.bwd_ws_bytes
+    budget = one + (full - one) // 5
+    adj = sk().api._AdjointPairs(offsets, pairs, d, 10, None, dev, budget)
+    assert adj.groups is not None and len(adj.groups) >= 5 and adj.peak_ws <= budget
+    Xt.grad = None
+    Yt.grad = None
+    m1 = sk().mmd2(Xt, Yt, order=10, check=True, ckpt_budget=budget)
+    m1.backward()
+    assert m1.item() == m0.item()
+    sc = max(gx0.abs().max().item(), gy0.abs().max().item())
+    assert (Xt.grad - gx0).abs().max().item() <= 1e-13 * sc
+    assert (Yt.grad - gy0).abs().max().item() <= 1e-13 * sc
+    assert sk().last_autograd_counters()["status"] == 0
+    # Gram: budgeted against unbudgeted
+    Xg = T(X, dev).requires_grad_(True)
+    G0 = sk().sigkernel_gram(Xg, order=10)
+    (G0 * T(np.arange(16.0).reshape(4, 4), dev)).sum().backward()
+    g0 = Xg.grad.clone()
+    Xg.grad = None
+    G1 = sk().sigkernel_gram(Xg, order=10, ckpt_budget=one)
+    (G1 * T(np.arange(16.0).reshape(4, 4), dev)).sum().backward()
+    assert torch.equal(G0, G1)
+    assert (Xg.grad - g0).abs().max().item() <= 1e-13 * g0.abs().max().item()
+
+
+def _mmd_pairs(X, Y):
+    """Offsets, the pair table of the XX, YY and XY blocks, and d (as mmd2 builds them)."""
+    nx, lx, d = X.shape
+    ny, ly, _ = Y.shape
+    offsets = np.concatenate([np.arange(nx + 1) * lx,
+                              nx * lx + np.arange(1, ny + 1) * ly]).astype(np.int64)
+    xi, xj = np.triu_indices(nx)
+    yi, yj = np.triu_indices(ny)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    pairs = np.concatenate([np.stack([xi, xj], 1), np.stack([nx + yi, nx + yj], 1),
+                            np.stack([ci.ravel(), nx + cj.ravel()], 1)]).astype(np.int32)
+    return offsets, pairs, d
+
+
 def test_mmd_full_size_finite_differences(dev):
     """Full MMD workload (32 + 32 paths, length 2048, d 8): autograd gradient vs
     central differences (h = 1e-6) on sampled coordinates."""
@@ -258,6 +312,30 @@ def test_gradient_fixed_and_runtime_depth(dev, order):
     assert np.abs(gx - gx0).max() <= 1e-10 * sc
     assert np.abs(gy - gy0).max() <= 1e-10 * sc
     assert sk().counters()["status"] == 0
+
+
+@pytest.mark.parametrize("sig,order", [(0.57, 12), (0.8, 16), (1.07, 16)])
+def test_very_rough_gradient(dev, sig, order):
+    """Cell coefficients |c| up to about 2-7 (the ragged workload's roughest
+    pairs reach ~7): segments whose bound allows |c| > 1/2 keep their cells'
+    left edges instead of recovering them from the right edges.  Value and
+    gradient against the oracle (1e-8); the order is the smallest compiled one
+    from the given one up whose forward raises no truncation warning."""
+    g = synth.rng(4400 + int(100 * sig))
+    x = np.cumsum(g.normal(size=(40, 3)) * sig, axis=0)
+    y = np.cumsum(g.normal(size=(35, 3)) * sig, axis=0)
+    c = np.abs(np.diff(x, axis=0) @ np.diff(y, axis=0).T).max()
+    assert c > {0.57: 1.5, 0.8: 3.0, 1.07: 5.0}[sig], c
+    for p in [p for p in sk()._lib.BWD_ORDERS if p >= order]:
+        sk().pair(T(x, dev), T(y, dev), order=p)
+        if not sk().counters()["status"] & sk()._lib.WARN_TRUNC:
+            break
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=p)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-10 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-8 * sc, (p, np.abs(gx - gx0).max() / sc)
+    assert np.abs(gy - gy0).max() <= 1e-8 * sc, (p, np.abs(gy - gy0).max() / sc)
 
 
 @pytest.mark.parametrize("order", [12, 16, 24])
