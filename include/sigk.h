@@ -210,6 +210,18 @@ int sigk_plan_set_outputs(sigk_plan* plan, const int64_t* out_index);
  */
 size_t sigk_plan_estimates_offset(const sigk_plan* plan);
 /*
+ * The plan's work order (host, diagnostics): the forward (adjoint != 0: the
+ * adjoint) ticket table as [n][2] (pair, strip) into out (host, cap pairs of
+ * int32; out NULL: only the count).  Every strip of every pair with cells
+ * appears once; a strip's producer (the strip below it in the forward, the
+ * strip above it in the adjoint) comes earlier, so a persistent workgroup
+ * never waits on a ticket nobody has claimed.  SIGK_EINVAL for plans of the
+ * one-call forms (their tables are built on the device; see
+ * sigk_ragged_tables) or cap < n.
+ */
+int sigk_plan_tickets(const sigk_plan* plan, int adjoint, int32_t* out, int64_t cap,
+                      int64_t* n_out);
+/*
  * Evaluate the batch: out[p] = k(path pairs[p][0], path pairs[p][1]).
  * pool: [sum len][d] FP64 device.  One persistent launch preceded by a small
  * reset kernel, no host-device copies: capturable in a HIP graph.
@@ -289,6 +301,17 @@ int sigk_plan_backward_checkpointed(const sigk_plan* plan, const double* pool,
  * SIGK_ERR_TABLE and contribute no gradient.  ws: at least
  * sigk_backward_workspace_size bytes.
  */
+/*
+ * Where the one-call forms build their ticket table in ws (host,
+ * diagnostics): byte offset of the [ntickets][2] int32 (pair, strip) table of
+ * sigk_gram_ragged (adjoint == 0) or of sigk_backward's adjoint order
+ * (adjoint != 0; its forward order sits at the offset returned for 0 with the
+ * same sizes), valid once the stream has passed the call.  Unused slots at
+ * the end hold pair -1.
+ */
+int sigk_ragged_tables(int64_t npaths, int64_t npairs, int64_t max_len, int64_t pool_points,
+                       int64_t d, const sigk_opts* o, int adjoint, size_t* tickets_offset,
+                       int64_t* ntickets);
 int sigk_backward_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,
                                  int64_t pool_points, int64_t d, const sigk_opts* o,
                                  size_t* bytes);

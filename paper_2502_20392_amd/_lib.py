@@ -82,6 +82,10 @@ SIGNATURES = {
     "sigk_plan_upload": (ctypes.c_int, [_P, _P, _SZ, _P]),
     "sigk_plan_set_outputs": (ctypes.c_int, [_P, _P]),
     "sigk_plan_estimates_offset": (_SZ, [_P]),
+    "sigk_plan_tickets": (ctypes.c_int, [_P, ctypes.c_int, _P, _I64, ctypes.POINTER(_I64)]),
+    "sigk_ragged_tables": (ctypes.c_int, [_I64, _I64, _I64, _I64, _I64, ctypes.POINTER(Opts),
+                                          ctypes.c_int, ctypes.POINTER(_SZ),
+                                          ctypes.POINTER(_I64)]),
     "sigk_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _SZ, _P]),
     "sigk_gram_ragged": (ctypes.c_int, [_P, _I64, _P, _I64, _I64, _P, _I64, _I64,
                                         ctypes.POINTER(Opts), _P, _P, _SZ, _P]),

@@ -690,6 +690,20 @@ int sigk_plan_set_outputs(sigk_plan* plan, const int64_t* out_index) {
 
 size_t sigk_plan_estimates_offset(const sigk_plan* plan) { return plan ? plan->o_est : 0; }
 
+int sigk_plan_tickets(const sigk_plan* plan, int adjoint, int32_t* out, int64_t cap,
+                      int64_t* n_out) {
+    if (!plan || !n_out || plan->dev_tables) return SIGK_EINVAL;
+    const std::vector<Ticket>& t = adjoint ? plan->tickets_rev : plan->tickets;
+    *n_out = (int64_t)t.size();
+    if (!out) return SIGK_OK;
+    if (cap < (int64_t)t.size()) return SIGK_EINVAL;
+    for (size_t i = 0; i < t.size(); ++i) {
+        out[2 * i] = t[i].pair;
+        out[2 * i + 1] = t[i].strip;
+    }
+    return SIGK_OK;
+}
+
 size_t sigk_plan_workspace_size(const sigk_plan* plan) { return plan ? plan->fwd_total : 0; }
 size_t sigk_plan_backward_workspace_size(const sigk_plan* plan) {
     return plan ? plan->bwd_total : 0;
@@ -1120,6 +1134,18 @@ int sigk_gram_ragged(const double* pool, int64_t pool_points, const int64_t* off
     rc = dev_tables(pl, offsets, pairs, out, (char*)ws, false, s);
     if (rc) return rc;
     return fwd_pass(&pl, pool, out, (char*)ws, s);
+}
+
+int sigk_ragged_tables(int64_t npaths, int64_t npairs, int64_t max_len, int64_t pool_points,
+                       int64_t d, const sigk_opts* o, int adjoint, size_t* tickets_offset,
+                       int64_t* ntickets) {
+    if (!tickets_offset || !ntickets) return SIGK_EINVAL;
+    sigk_plan pl;
+    const int rc = dev_plan(npaths, npairs, max_len, pool_points, d, o, adjoint != 0, pl);
+    if (rc) return rc;
+    *tickets_offset = adjoint ? pl.o_tkr : pl.o_tk;
+    *ntickets = pl.ntk;
+    return SIGK_OK;
 }
 
 int sigk_backward_workspace_size(int64_t npaths, int64_t npairs, int64_t max_len,

@@ -314,28 +314,31 @@ def test_gradient_fixed_and_runtime_depth(dev, order):
     assert sk().counters()["status"] == 0
 
 
-@pytest.mark.parametrize("sig,order", [(0.57, 12), (0.8, 16), (1.07, 16)])
+@pytest.mark.parametrize("sig,order", [(0.57, 12), (1.07, 16), (1.3, 20)])
 def test_very_rough_gradient(dev, sig, order):
-    """Cell coefficients |c| up to about 2-7 (the ragged workload's roughest
-    pairs reach ~7): segments whose bound allows |c| > 1/2 keep their cells'
-    left edges instead of recovering them from the right edges.  Value and
-    gradient against the oracle (1e-8); the order is the smallest compiled one
-    from the given one up whose forward raises no truncation warning."""
+    """Cell coefficients |c| up to 3.9, 5.8 and 13.1 (the ragged workload's
+    roughest pairs reach ~7): segments whose bound allows |c| > 1/2 keep their
+    cells' left edges instead of recovering them from the right edges, whose
+    recovery loses digits as e^|c| per step (measured: 2e-9 at |c| = 13 and
+    1e-7 at 20 without it, 1e-12 with it).  Value and gradient against the
+    oracle (1e-10); the order is the smallest compiled one from the given one
+    up whose forward raises no truncation warning."""
     g = synth.rng(4400 + int(100 * sig))
     x = np.cumsum(g.normal(size=(40, 3)) * sig, axis=0)
     y = np.cumsum(g.normal(size=(35, 3)) * sig, axis=0)
     c = np.abs(np.diff(x, axis=0) @ np.diff(y, axis=0).T).max()
-    assert c > {0.57: 1.5, 0.8: 3.0, 1.07: 5.0}[sig], c
+    assert c > {0.57: 3.5, 1.07: 5.5, 1.3: 13.0}[sig], c
     for p in [p for p in sk()._lib.BWD_ORDERS if p >= order]:
         sk().pair(T(x, dev), T(y, dev), order=p)
         if not sk().counters()["status"] & sk()._lib.WARN_TRUNC:
             break
+    assert sk().counters()["status"] == 0
     k0, gx0, gy0 = oracle.grad(x, y)
     k, gx, gy = gpu_pair_grad(x, y, dev, order=p)
     sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
     assert abs(k - k0) <= 1e-10 * max(1, abs(k0))
-    assert np.abs(gx - gx0).max() <= 1e-8 * sc, (p, np.abs(gx - gx0).max() / sc)
-    assert np.abs(gy - gy0).max() <= 1e-8 * sc, (p, np.abs(gy - gy0).max() / sc)
+    assert np.abs(gx - gx0).max() <= 1e-10 * sc, (p, np.abs(gx - gx0).max() / sc)
+    assert np.abs(gy - gy0).max() <= 1e-10 * sc, (p, np.abs(gy - gy0).max() / sc)
 
 
 @pytest.mark.parametrize("order", [12, 16, 24])

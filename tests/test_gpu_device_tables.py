@@ -132,3 +132,48 @@ def test_invalid_table_entries(dev):
     # a valid table on the same workspace size clears the bit
     out = sk().gram_ragged(pd, off, pairs, order=16)
     assert sk().counters()["status"] == 0
+
+
+def _tables(ws, npaths, npairs, max_len, pool_points, d, order, adjoint):
+    """The ticket table a one-call form left in ws: [ntickets, 2] (pair, strip)."""
+    import ctypes
+    lib = sk()._lib
+    o = lib.make_opts(order)
+    off, n = ctypes.c_size_t(), ctypes.c_int64()
+    lib.check(lib.load().sigk_ragged_tables(npaths, npairs, max_len, pool_points, d,
+                                            ctypes.byref(o), adjoint, ctypes.byref(off),
+                                            ctypes.byref(n)))
+    raw = ws[off.value: off.value + 8 * n.value].view(torch.int32).reshape(-1, 2)
+    return raw.cpu().numpy()
+
+
+@pytest.mark.parametrize("adjoint", [0, 1])
+def test_device_ticket_order(dev, adjoint):
+    """The ticket tables the one-call forms build on the device: every strip of
+    every pair with cells once, a strip's producer (the strip below it in the
+    forward order, the one above it in the adjoint order) earlier, and the
+    unused slots (pairs shorter than max_len) at the end as pair -1."""
+    pool, off, pairs = batch(7400, n_paths=12, lmin=1, lmax=600)
+    max_len = int(np.diff(off).max())
+    pd, offd, prd = T(pool, dev), T(off, dev), T(pairs, dev)
+    if adjoint:
+        sk().backward(pd, offd, prd, torch.ones(len(pairs), dtype=torch.float64, device=dev),
+                      max_len=max_len, order=8)
+    else:
+        sk().gram_ragged(pd, offd, prd, max_len=max_len, order=8)
+    torch.cuda.synchronize()
+    tk = _tables(sk().last_workspace(), len(off) - 1, len(pairs), max_len, pool.shape[0],
+                 pool.shape[1], 8, adjoint)
+    lens = np.diff(off)
+    strips = [((lens[b] - 1 + 63) // 64) if lens[a] >= 2 and lens[b] >= 2 else 0
+              for a, b in pairs]
+    used = tk[tk[:, 0] >= 0]
+    assert len(used) == sum(strips)
+    assert (tk[len(used):, 0] == -1).all()  # unused slots close the table
+    pos = {(int(p), int(s)): i for i, (p, s) in enumerate(used)}
+    assert len(pos) == len(used)
+    assert set(pos) == {(p, s) for p, n in enumerate(strips) for s in range(n)}
+    for (p, s), i in pos.items():
+        prod = (p, s + 1) if adjoint else (p, s - 1)
+        if prod in pos:
+            assert pos[prod] < i, (p, s)

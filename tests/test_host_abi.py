@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
     for must in ("sigk_pair", "sigk_gram", "sigk_plan_ragged", "sigk_plan_run",
                  "sigk_plan_backward", "sigk_read_status"):
         assert must in names
-    assert len(names) == 32
+    assert len(names) == 34
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -212,6 +212,46 @@ def test_plan_rejections(lib, case, code):
     rc, plan = make_plan(lib, offsets, pairs, d, order)
     assert rc == code
     assert not plan.value  # no plan is returned on failure
+
+
+def check_ticket_order(tickets, strips, adjoint):
+    """Every (pair, strip) of the batch exactly once; a strip's producer first."""
+    pos = {}
+    for i, (p, s) in enumerate(tickets):
+        assert (p, s) not in pos
+        pos[(p, s)] = i
+    want = {(p, s) for p, n in enumerate(strips) for s in range(n)}
+    assert set(pos) == want
+    for (p, s), i in pos.items():
+        prod = (p, s + 1) if adjoint else (p, s - 1)
+        if prod in pos:
+            assert pos[prod] < i, (p, s)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plan_ticket_order(lib, seed):
+    """The host plan's forward and adjoint work orders: complete, and every
+    producer strip ahead of its consumer (the condition under which persistent
+    workgroups that wait on each other cannot deadlock)."""
+    _, offs, pairs = random_batch(seed, npaths=14, lo=0, hi=700, npairs=40)
+    rc, plan = make_plan(lib, offs, pairs, 4, order=8)
+    assert rc == 0
+    try:
+        lens = np.diff(np.asarray(offs))
+        strips = [((lens[b] - 1 + 63) // 64) if lens[a] >= 2 and lens[b] >= 2 else 0
+                  for a, b in pairs]
+        for adjoint in (0, 1):
+            n = ctypes.c_int64()
+            assert lib.sigk_plan_tickets(plan, adjoint, None, 0, ctypes.byref(n)) == 0
+            assert n.value == sum(strips)
+            buf = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+            assert lib.sigk_plan_tickets(plan, adjoint, buf.ctypes.data, n.value - 1,
+                                         ctypes.byref(n)) == (-1 if n.value > 0 else 0)
+            assert lib.sigk_plan_tickets(plan, adjoint, buf.ctypes.data, n.value,
+                                         ctypes.byref(n)) == 0
+            check_ticket_order([tuple(t) for t in buf[: n.value]], strips, adjoint)
+    finally:
+        lib.sigk_plan_destroy(plan)
 
 
 def test_plan_output_slots(lib):
