@@ -37,7 +37,9 @@ struct Variant {
 #define SIGK_V_FWD(P, D) {P, D, launch_fwd_##P##_##D, occupancy_fwd_##P##_##D, nullptr, nullptr, nullptr, nullptr},
 const Variant kFwdTable[] = {SIGK_FWD_VARIANTS(SIGK_V_FWD)};
 #undef SIGK_V_FWD
-#define SIGK_V_BWD(P, D) {P, D, nullptr, nullptr, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_ckpt_##P##_##D, occupancy_bwd_##P##_##D},
+// (the adjoint variants' fwd slot is the first sweep of a long pair's
+// gradient, the lines kernel)
+#define SIGK_V_BWD(P, D) {P, D, launch_lines_##P##_##D, occupancy_lines_##P##_##D, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_ckpt_##P##_##D, occupancy_bwd_##P##_##D},
 const Variant kBwdTable[] = {SIGK_BWD_VARIANTS(SIGK_V_BWD)};
 #undef SIGK_V_BWD
 #define SIGK_V_FWDSQ(P, D) {P, D, launch_fwdsq_##P##_##D, occupancy_fwdsq_##P##_##D, nullptr, nullptr, nullptr, nullptr},
@@ -97,7 +99,7 @@ int g_cus[64] = {0};
 
 // resident workgroups per device for a variant's forward, adjoint or
 // checkpoint kernel (their register and LDS footprints differ)
-enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2, kKernelFwdSq = 3 };
+enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2, kKernelFwdSq = 3, kKernelLines = 4 };
 
 int device_wgs(int P, int D, int kind) {
     int dev = 0;
@@ -116,7 +118,10 @@ int device_wgs(int P, int D, int kind) {
         occ = v ? v->occ_fwd() : 0;
     } else {
         const Variant* v = find_bwd(P, D);
-        occ = v ? (kind == kKernelBwd ? v->occ_bwd() : v->occ_ckpt()) : 0;
+        occ = v ? (kind == kKernelBwd    ? v->occ_bwd()
+                   : kind == kKernelLines ? v->occ_fwd()
+                                          : v->occ_ckpt())
+                : 0;
     }
     if (occ < 1) occ = 1;
     int value = occ * (dev < 64 ? g_cus[dev] : 256);
@@ -1374,7 +1379,8 @@ int sigk_pair_backward(const double* x, int64_t lx, const double* y, int64_t ly,
     a.frontier = (double*)(base + L.o_front);
     a.progress = prog;
     a.trunc_est = est;
-    e = v->ckpt(a, (int)std::min<int64_t>(cgrid, L.S), s);
+    const int lgrid = std::max(device_wgs(L.P, L.D, kKernelLines), 1);
+    e = v->fwd(a, (int)std::min<int64_t>(lgrid, L.S), s);
     if (e == hipSuccess) e = launch_finalize(hdr, est, 1, budget_of(op), s);
     if (e != hipSuccess) return device_error(e);
 

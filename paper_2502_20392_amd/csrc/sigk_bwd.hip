@@ -40,11 +40,9 @@ template <int P, int D>
 constexpr int ckpt_chunk = (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
 
 // Modes: kModeTable, the checkpointing sweep of a batch (snap: per-strip
-// frontier rows); kModeLines, the plain sweep of one long pair keeping the
-// block-boundary lines (snap: the in-place frontier row, no checkpoints);
-// kModeBlock, the checkpointing sweep of the blocks of one anti-diagonal
-// (snap: per-slot frontier rows; strip 0 reads its bottom line, column 0
-// its left line).
+// frontier rows); kModeBlock, the checkpointing sweep of the blocks of one
+// anti-diagonal (snap: per-slot frontier rows; strip 0 reads its bottom line,
+// column 0 its left line).
 template <int P, int D>
 __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
     constexpr int CH = ckpt_chunk<P, D>, RB = CH == 64 ? 128 : ring_cols(P);
@@ -68,10 +66,6 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
             if (pair < 0) break;  // unused slots close a table built on the device
             g = resolve(a, pair, P, 0);
             g.front = a.desc[pair].snap_off;
-        } else if (a.mode == kModeLines) {
-            pair = 0;
-            strip = (int)t;
-            g = resolve_lines(a);
         } else {
             pair = (int)(t % (unsigned)a.blk.nb);
             strip = (int)(t / (unsigned)a.blk.nb);
@@ -82,30 +76,58 @@ __global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
         S.pair = pair;
         S.prog = a.progress + g.prog;
         const int64_t row = (int64_t)g.m * P;
-        if (a.mode == kModeLines) {
-            // in-place frontier row, except across block-row boundaries
-            const int kb = a.blk.kb;
-            double* own = snap;
-            S.Fin = (strip > 0 && strip % kb == 0)
-                        ? a.blk.hline + (int64_t)(strip / kb - 1) * row
-                        : own;
-            S.Fout = ((strip + 1) % kb == 0 && (int64_t)(strip + 1) * kWave < g.n)
-                         ? a.blk.hline + (int64_t)((strip + 1) / kb - 1) * row
-                         : own;
-            S.ck = nullptr;
-            S.ckq = nullptr;
-            S.ck_every = 1;
-            S.vl = a.blk.nj > 1 ? a.blk.vline : nullptr;
-        } else {
-            S.Fin = (strip == 0 && r.bot) ? r.bot : snap + g.front + (int64_t)strip * row;
-            S.Fout = snap + g.front + (int64_t)(strip + 1) * row;
-            double* ck = a.ckpt + g.ckpt + (int64_t)strip * ckpt_strip_doubles(g.m, P);
-            S.ck = ck;
-            S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
-            S.ck_every = kCkptEvery;
-            S.left = r.left;
-            S.below_line = r.bot != nullptr;
-        }
+        S.Fin = (strip == 0 && r.bot) ? r.bot : snap + g.front + (int64_t)strip * row;
+        S.Fout = snap + g.front + (int64_t)(strip + 1) * row;
+        double* ck = a.ckpt + g.ckpt + (int64_t)strip * ckpt_strip_doubles(g.m, P);
+        S.ck = ck;
+        S.ckq = ck + ckpt_states(g.m) * 2 * P * kWave;
+        S.ck_every = kCkptEvery;
+        S.left = r.left;
+        S.below_line = r.bot != nullptr;
+        if (!S.sweep()) break;
+    }
+    if (lane == 0) {
+        atomicAdd(&a.hdr->cells, acc.cells);
+        atomicAdd(&a.hdr->flops, acc.flops);
+        if (acc.status) atomicOr(&a.hdr->status, acc.status);
+    }
+}
+
+// The first sweep of a long pair's gradient (kModeLines): the plain forward
+// sweep of the whole pair, with the plain forward kernel's chunks and
+// occupancy, writing k(x, y) and keeping the block-boundary lines: a strip
+// that ends a block row writes its top edges to that row's line instead of
+// the in-place frontier row (the next strip reads them there), and every
+// lane stores its right edge at the last column of each block column.
+template <int P, int D>
+__global__ void __launch_bounds__(kWave)
+    __attribute__((amdgpu_waves_per_eu(P <= 6 && D <= 8 ? 3 : 1))) lines_kernel(FwdArgs a) {
+    constexpr int CH = fwd_chunk_cols(P, D), RB = fwd_ring_cols(P, D);
+    __shared__ LdsStrip<P, D, CH, RB> L;
+    Acc acc;
+    const int lane = lane_id();
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&a.hdr->ticket, 1u);
+        t = (unsigned)uniform((int)t);
+        if ((int64_t)t >= a.ntickets) break;
+        if (uniform((int)(load_status(a.hdr) & SIGK_ERR_WATCHDOG))) break;
+        const int strip = (int)t;
+        Geo g = resolve_lines(a);
+        StripCtx<P, D, CH, RB, false, true> S(a, g, L, acc, strip);
+        S.pair = 0;
+        S.prog = a.progress;
+        const int64_t row = (int64_t)g.m * P;
+        const int kb = a.blk.kb;
+        S.Fin = (strip > 0 && strip % kb == 0) ? a.blk.hline + (int64_t)(strip / kb - 1) * row
+                                               : a.frontier;
+        S.Fout = ((strip + 1) % kb == 0 && (int64_t)(strip + 1) * kWave < g.n)
+                     ? a.blk.hline + (int64_t)((strip + 1) / kb - 1) * row
+                     : a.frontier;
+        S.ck = nullptr;
+        S.ckq = nullptr;
+        S.ck_every = 1;
+        S.vl = a.blk.nj > 1 ? a.blk.vline : nullptr;
         if (!S.sweep()) break;
     }
     if (lane == 0) {
@@ -576,6 +598,19 @@ hipError_t SIGK_NAME(launch_ckpt_, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, h
     hipLaunchKernelGGL((ckpt_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, a,
                        a.frontier);
     return hipGetLastError();
+}
+
+hipError_t SIGK_NAME(launch_lines_, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((lines_kernel<SIGK_P, SIGK_D>), dim3(grid), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+int SIGK_NAME(occupancy_lines_, SIGK_P, SIGK_D)() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lines_kernel<SIGK_P, SIGK_D>, kWave,
+                                                     0) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 hipError_t SIGK_NAME(launch_bwd_, SIGK_P, SIGK_D)(const BwdArgs& b, int grid, hipStream_t s) {

@@ -208,6 +208,8 @@ SIGK_FWDSQ_VARIANTS(SIGK_DECL_FWDSQ)
 // mode with delta set), on the matrix cores.
 hipError_t launch_delta_gemm(const FwdArgs& a, hipStream_t s);
 #define SIGK_DECL_BWD(P, D) \
+    hipError_t launch_lines_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_lines_##P##_##D(); \
     hipError_t launch_ckpt_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
     hipError_t launch_bwd_##P##_##D(const BwdArgs& a, int grid, hipStream_t s); \
     int occupancy_ckpt_##P##_##D(); \

@@ -322,7 +322,7 @@ def test_very_rough_gradient(dev, sig, order):
     recovery loses digits as e^|c| per step (measured: 2e-9 at |c| = 13 and
     1e-7 at 20 without it, 1e-12 with it).  Value and gradient against the
     oracle (1e-10); the order is the smallest compiled one from the given one
-    up whose forward raises no truncation warning."""
+    up whose forward raises no truncation warning, else 24."""
     g = synth.rng(4400 + int(100 * sig))
     x = np.cumsum(g.normal(size=(40, 3)) * sig, axis=0)
     y = np.cumsum(g.normal(size=(35, 3)) * sig, axis=0)
@@ -332,7 +332,9 @@ def test_very_rough_gradient(dev, sig, order):
         sk().pair(T(x, dev), T(y, dev), order=p)
         if not sk().counters()["status"] & sk()._lib.WARN_TRUNC:
             break
-    assert sk().counters()["status"] == 0
+    # (the estimate is conservative: at |c| near 6 and above order 24 still
+    # warns while matching the oracle; only a non-finite value would fail)
+    assert not sk().counters()["status"] & ~sk()._lib.WARN_TRUNC
     k0, gx0, gy0 = oracle.grad(x, y)
     k, gx, gy = gpu_pair_grad(x, y, dev, order=p)
     sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
