@@ -43,8 +43,12 @@ constexpr int ckpt_chunk = (P >= 10 && P <= 20 && D <= 16) ? 64 : 32;
 // frontier rows); kModeBlock, the checkpointing sweep of the blocks of one
 // anti-diagonal (snap: per-slot frontier rows; strip 0 reads its bottom line,
 // column 0 its left line).
+// (three waves per SIMD at orders 4-5 with d <= 8: 168 registers, 7% faster
+// at order 5; at order 6 that limit would spill)
 template <int P, int D>
-__global__ void __launch_bounds__(kWave) ckpt_kernel(FwdArgs a, double* snap) {
+__global__ void __launch_bounds__(kWave)
+    __attribute__((amdgpu_waves_per_eu(P <= 5 && D <= 8 ? 3 : 1))) ckpt_kernel(FwdArgs a,
+                                                                              double* snap) {
     constexpr int CH = ckpt_chunk<P, D>, RB = CH == 64 ? 128 : ring_cols(P);
     __shared__ LdsStrip<P, D, CH, RB> L;
     Acc acc;
@@ -146,7 +150,10 @@ struct LdsBwd {
     // Per-chunk Neumann depths are still read at the checkpointing sweep's
     // chunk width (depth_at).
     static constexpr int ACH = (P >= 10 && P <= 12 && D <= 8) ? 64 : 32;
-    static constexpr int ARB = ACH == 64 ? 128 : ring_cols(P);
+    // (96 columns hold a 32-column chunk and the 63 before it; at orders 4-5
+    // with d <= 8 the smaller rings let an eighth wave per CU fit its LDS:
+    // 4.5% faster there than with 128)
+    static constexpr int ARB = ACH == 64 ? 128 : 96;
     static_assert(ARB >= ACH + kWave - 1,
                   "the rings must hold a chunk and the 63 columns before it");
     double dx[D * ARB];      // increments of x by ring slot

@@ -267,33 +267,40 @@ def test_mmd_full_size_finite_differences(dev):
     assert np.abs(grad.sum(axis=1)).max() <= 1e-10 * max(1, np.abs(grad).max())
 
 
-@pytest.mark.timeout(300)
-def test_mmd_cross_block_full_size_sampled_pair(dev):
+@pytest.mark.timeout(600)
+def test_mmd_cross_block_full_size_sampled_pairs(dev):
     """The cross block of the MMD workload (32 x 32 pairs of length 2048, d 8)
-    at order 12 in one launch, with output weight 1 on one pair and 0 on the
-    rest: the gradients of that pair's two paths against the oracle's, the
-    pair's value against the oracle's, every other path's gradient exactly 0."""
+    at order 12 in one launch, with distinct output weights on six pairs whose
+    paths are all different and 0 on the rest: each of those twelve paths'
+    gradients against the oracle's for its pair (weighted), the pairs' values
+    against the oracle's, every other path's gradient exactly 0.  The oracle's
+    gradients run in parallel threads."""
+    from concurrent.futures import ThreadPoolExecutor
     X, Y = synth.mmd_sets()
     n, L, d = X.shape
     pool = np.concatenate([X.reshape(-1, d), Y.reshape(-1, d)])
     off = np.arange(2 * n + 1, dtype=np.int64) * L
     pairs = np.array([[i, n + j] for i in range(n) for j in range(n)], dtype=np.int32)
-    i0, j0 = 3, 7
+    chosen = [(3, 7, 1.0), (10, 20, -0.5), (25, 1, 2.0), (31, 31, 0.25), (0, 16, -3.0),
+              (17, 0, 1.5)]
     w = np.zeros(len(pairs))
-    w[i0 * n + j0] = 1.0
+    for i, j, wt in chosen:
+        w[i * n + j] = wt
     plan = sk().RaggedPlan(off, pairs, d, order=12, device=dev)
     pd = T(pool, dev)
     kv = plan.run(pd).cpu().numpy()
     assert sk().counters()["status"] == 0
     gp = plan.backward(pd, T(w, dev)).cpu().numpy().reshape(2 * n, L, d)
     assert sk().counters()["status"] == 0
-    k0, gx0, gy0 = oracle.grad(X[i0], Y[j0])
-    assert abs(kv[i0 * n + j0] - k0) <= 1e-12 * max(1, abs(k0))
-    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
-    assert np.abs(gp[i0] - gx0).max() <= 1e-10 * sc
-    assert np.abs(gp[n + j0] - gy0).max() <= 1e-10 * sc
+    with ThreadPoolExecutor(len(chosen)) as ex:
+        refs = list(ex.map(lambda c: oracle.grad(X[c[0]], Y[c[1]]), chosen))
     rest = np.ones(2 * n, dtype=bool)
-    rest[[i0, n + j0]] = False
+    for (i, j, wt), (k0, gx0, gy0) in zip(chosen, refs):
+        assert abs(kv[i * n + j] - k0) <= 1e-12 * max(1, abs(k0))
+        sc = abs(wt) * max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+        assert np.abs(gp[i] - wt * gx0).max() <= 1e-10 * sc, (i, j)
+        assert np.abs(gp[n + j] - wt * gy0).max() <= 1e-10 * sc, (i, j)
+        rest[[i, n + j]] = False
     assert not np.any(gp[rest])
 
 
