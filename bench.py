@@ -92,6 +92,27 @@ def traffic_from_profile(order):
     return t.get("hbm_bytes_per_launch")
 
 
+def cell_flops(P, q, d):
+    """Algorithmic flops of one cell's map at edge order P, Neumann depth q, d
+    channels (FMA = 2), the count the kernels add up on the device."""
+    return 4 * P - 6 + q * (8 * P - 2) - 2 * q * (q + 1) - (1 if q > 0 else 0) + 2 * d
+
+
+def mean_depth(P, d, flops_per_cell):
+    """The Neumann depth q at which cell_flops(P, q, d) equals the measured
+    flops per cell (the device count), interpolated between integers: the
+    cells' mean depth where it is a whole number, else a summary of the mix."""
+    prev = None
+    for q in range(P):
+        f = cell_flops(P, q, d)
+        if abs(f - flops_per_cell) < 1e-9:
+            return float(q)
+        if prev is not None and prev < flops_per_cell < f:
+            return q - 1 + (flops_per_cell - prev) / (f - prev)
+        prev = f
+    return None
+
+
 def timed(fn, torch, steps=3):
     s = torch.cuda.current_stream()
     fn()
@@ -460,6 +481,8 @@ def main():
                      "traffic": traffic, "kernel": f"fwd_kernel<{cnt['order']}, 8>",
                      "flops_per_launch": cnt["flops"],
                      "flops_per_cell": cnt["flops"] / max(cnt["cells"], 1),
+                     "neumann_depth": mean_depth(cnt["order"], int(x.shape[1]),
+                                                 cnt["flops"] / max(cnt["cells"], 1)),
                      "kernel_ms": float(np.mean(kernel_ms))},
         "peak_mem_bytes": int(torch.cuda.max_memory_allocated(dev)),
         "kernel_source_digest": kernel_source_digest(),
