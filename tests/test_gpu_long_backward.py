@@ -9,8 +9,10 @@ checkpointing adjoint (sigk_backward) on the same pair; degenerate sizes.  At
 the full size of the 1,000,000-point workload (d 8, fBM H 0.2, edge order 5)
 the oracle is out of reach; there the checks are identities of the kernel:
 k(x, y) as the forward sweep computes it, the scaling duality
-sum_i <dk/dx_i, x_i> = sum_j <dk/dy_j, y_j> (k(lx, y) = k(x, ly)), and
-subdivision invariance: with x the workload's path taken at every 1,000th
+sum_i <dk/dx_i, x_i> = sum_j <dk/dy_j, y_j> (k(lx, y) = k(x, ly)),
+translation invariance (each path's gradient sums to zero), the closed-form
+gradients of d = 1 paths and of a straight x against any y, the oracle on a
+2,001-point prefix, and subdivision invariance: with x the workload's path taken at every 1,000th
 point and each of its 999 segments subdivided 1,000 times (999,001 points),
 k equals the oracle's value on the coarse pair (stored), dk/dy equals that of
 the coarse pair and the fine dk/dx summed back onto the coarse points equals
@@ -198,3 +200,78 @@ def test_long_pair_gradient_full_size(dev):
     ey = np.abs(gy - gy0).max() / scy
     print(f"subdivision: rel err dk/dx {ex:.3e}, dk/dy {ey:.3e}", flush=True)
     assert ex <= 1e-8 and ey <= 1e-8
+    # translation invariance: the gradient of each path sums to zero
+    assert np.abs(gx.sum(axis=0)).max() <= 1e-12 * np.abs(gx).sum()
+    assert np.abs(gy.sum(axis=0)).max() <= 1e-12 * np.abs(gy).sum()
+
+
+def ladder(x, y, dev):
+    """The smallest compiled order from 5 up whose forward raises no truncation
+    warning on this pair (the benchmark's rule)."""
+    for p in [p for p in sk()._lib.BWD_ORDERS if p >= 5]:
+        sk().pair(T(x, dev), T(y, dev), order=p)
+        if not sk().counters()["status"] & sk()._lib.WARN_TRUNC:
+            return p
+    return p
+
+
+@pytest.mark.timeout(600)
+def test_long_pair_gradient_closed_forms(dev):
+    """Full length (1,000,000 points), default blocks, at the smallest order
+    whose forward raises no truncation warning.  (a) d = 1: k
+    depends only on the total increments X, Y, k = I0(2 sqrt(XY)), so the
+    interior gradients vanish and the end points carry -/+ Y I1(2 sqrt(XY)) /
+    sqrt(XY) (with respect to x; X for y).  (b) x a straight segment with
+    increment a, y the workload's path: k = I0(2 sqrt(<a, Y>)) for every y, so
+    dk/dy vanishes inside and is -/+ a I1(2 sqrt(z))/sqrt(z), z = <a, Y>, at
+    the ends of y."""
+    import scipy.special as sp
+    g = synth.rng(6500)
+    n = 1_000_000
+    x = np.cumsum(g.normal(size=(n, 1)) / np.sqrt(n), axis=0)
+    y = np.cumsum(g.normal(size=(n, 1)) / np.sqrt(n), axis=0)
+    X, Y = float(x[-1, 0] - x[0, 0]), float(y[-1, 0] - y[0, 0])
+    order = ladder(x, y, dev)
+    k, gx, gy = sk().pair_backward(T(x, dev), T(y, dev), order=order)
+    assert sk().counters()["status"] == 0
+    z = X * Y
+    f = (sp.i0(2 * np.sqrt(z)), sp.i1(2 * np.sqrt(z)) / np.sqrt(z)) if z > 0 else \
+        (sp.j0(2 * np.sqrt(-z)), sp.j1(2 * np.sqrt(-z)) / np.sqrt(-z))
+    assert abs(k.item() - f[0]) <= 1e-10 * max(1.0, abs(f[0]))
+    gx = gx.cpu().numpy()[:, 0]
+    gy = gy.cpu().numpy()[:, 0]
+    ex = np.array([-Y * f[1], Y * f[1]])
+    ey = np.array([-X * f[1], X * f[1]])
+    sc = max(abs(ex).max(), abs(ey).max())
+    assert np.abs(gx[[0, -1]] - ex).max() <= 1e-9 * sc
+    assert np.abs(gy[[0, -1]] - ey).max() <= 1e-9 * sc
+    assert np.abs(gx[1:-1]).max() <= 1e-9 * sc and np.abs(gy[1:-1]).max() <= 1e-9 * sc
+    # (b)
+    xw, yw = synth.long_pair()
+    a = xw[-1] - xw[0]
+    xl = np.linspace(0.0, 1.0, len(xw))[:, None] * a[None, :]
+    Yw = yw[-1] - yw[0]
+    z = float(a @ Yw)
+    df = sp.i1(2 * np.sqrt(z)) / np.sqrt(z) if z > 0 else sp.j1(2 * np.sqrt(-z)) / np.sqrt(-z)
+    k, _, gy = sk().pair_backward(T(xl, dev), T(yw, dev), order=ladder(xl, yw, dev))
+    assert sk().counters()["status"] == 0
+    gy = gy.cpu().numpy()
+    sc = np.abs(a * df).max()
+    assert np.abs(gy[0] + a * df).max() <= 1e-9 * sc
+    assert np.abs(gy[-1] - a * df).max() <= 1e-9 * sc
+    assert np.abs(gy[1:-1]).max() <= 1e-9 * sc
+
+
+@pytest.mark.timeout(300)
+def test_long_pair_gradient_prefix_vs_oracle(dev):
+    """The workload's first 2,001 points of each path (4e6 cells) with the
+    default blocks, against the oracle's value and gradient."""
+    x, y = synth.long_pair()
+    x, y = x[:2001], y[:2001]
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy, st = block_grad(x, y, dev, order=5, rows=256, cols=300)
+    sc = max(1e-300, np.abs(gx0).max(), np.abs(gy0).max())
+    assert st == 0
+    assert abs(k - k0) <= 1e-12 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-9 * sc
+    assert np.abs(gy - gy0).max() <= 1e-9 * sc
