@@ -210,17 +210,18 @@ def ragged(torch, sk, dev, synth, tune, frac, res):
     pd = torch.from_numpy(pool).to(dev)
     tuned = tune.tune_ragged(pd, off, pairs, hint=16, use_cache=False)
     plan = sk.RaggedPlan(off, pairs, pool.shape[1], order=tuned["order"], grid=tuned["grid"],
-                         device=dev)
+                         tile=tuned["tile"], device=dev)
     out = torch.empty(plan.npairs, dtype=torch.float64, device=dev)
     g = plan.capture(pd, out)
     ms = timed(g.replay, torch)
     c = sk.counters(plan.ws)
     uniform = {"cells_per_s": plan.cells / (ms / 1e3), "ms": ms, "order": tuned["order"],
-               "grid": tuned["grid"], "flops": c["flops"], "fp64_frac": frac(c["flops"], ms),
-               "status": c["status"]}
+               "grid": tuned["grid"], "tile": tuned["tile"], "tile_trials": tuned["trials"],
+               "flops": c["flops"], "fp64_frac": frac(c["flops"], ms), "status": c["status"]}
     # per-pair orders: one launch per order class, all in one graph
     orders, rungs = tune.tune_ragged_orders(pd, off, pairs, hint=FIRST_ORDER)
-    cp = sk.OrderClassPlan(off, pairs, pool.shape[1], orders, device=dev)
+    tiles, tile_trials = tune.tune_class_tiles(pd, off, pairs, orders)
+    cp = sk.OrderClassPlan(off, pairs, pool.shape[1], orders, device=dev, tiles=tiles)
     out2 = torch.empty(len(pairs), dtype=torch.float64, device=dev)
     g2 = cp.capture(pd, out2)
     ms2 = timed(g2.replay, torch)
@@ -228,6 +229,7 @@ def ragged(torch, sk, dev, synth, tune, frac, res):
     diff = (out2 - out).abs() / out.abs().clamp(min=1.0)
     per_pair = {"cells_per_s": cp.cells / (ms2 / 1e3), "ms": ms2,
                 "classes": {str(k): v for k, v in sorted(cp.classes.items())}, "rungs": rungs,
+                "tiles": {str(k): v for k, v in sorted(tiles.items())}, "tile_trials": tile_trials,
                 "flops": c2["flops"], "fp64_frac": frac(c2["flops"], ms2),
                 "status": c2["status"], "max_rel_diff_vs_uniform": float(diff.max())}
     res["ragged512_len64to4096_d32_graph"] = {

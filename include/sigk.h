@@ -94,7 +94,12 @@ typedef struct sigk_opts {
                           (4,5,6,8,10,12,16,20,24).                               */
     int32_t grid;      /* persistent workgroups; 0 = fill the device              */
     uint32_t flags;    /* SIGK_FLAG_*                                              */
-    int32_t reserved;
+    int32_t tile_cols; /* work tile of the forward sweeps with d <= 32: 64 grid
+                          rows x tile_cols columns per frontier chunk.  0 = the
+                          compiled default for (order, d); the other compiled
+                          width (32 or 64) may be chosen, e.g. by an autotuner;
+                          any other value gives SIGK_EUNSUPPORTED.  The
+                          checkpointing and adjoint sweeps ignore it.           */
 } sigk_opts;
 
 typedef struct sigk_counters {
@@ -395,6 +400,10 @@ int sigk_read_status(const void* ws, uint32_t* status_bits, void* stream);
 const char* sigk_strerror(int code);
 /* Compiled edge orders and dimension buckets (host). */
 int sigk_supported_order(int order); /* smallest compiled P >= order, or 0 */
+/* Forward work-tile widths (sigk_opts.tile_cols) compiled for this order and
+   d (host): the default (alternative == 0) or the other one; 0 if none (d > 32
+   has only the default of the coefficient-field sweep). */
+int sigk_tile_cols(int order, int64_t d, int alternative);
 /* Persistent workgroups that fill the current device for this variant (host;
    queries the HIP runtime, no device work).  0 if the variant does not exist. */
 int sigk_device_grid(int order, int64_t d, int backward);

@@ -41,7 +41,7 @@ class SigkError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("tail_tol", ctypes.c_double),
                 ("order", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("tile_cols", ctypes.c_int32)]
 
 
 class Counters(ctypes.Structure):
@@ -61,6 +61,7 @@ _SZ = ctypes.c_size_t
 SIGNATURES = {
     "sigk_default_opts": (None, [ctypes.POINTER(Opts)]),
     "sigk_supported_order": (ctypes.c_int, [ctypes.c_int]),
+    "sigk_tile_cols": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int]),
     "sigk_device_grid": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int]),
     "sigk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sigk_pair_workspace_size": (ctypes.c_int, [_I64, _I64, _I64, ctypes.POINTER(Opts),
@@ -141,7 +142,7 @@ def check(rc):
 
 
 def make_opts(order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, square=False,
-              field=False):
+              field=False, tile=0):
     o = Opts()
     load().sigk_default_opts(ctypes.byref(o))
     if order is not None:
@@ -153,4 +154,5 @@ def make_opts(order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, squa
     o.grid = int(grid)
     o.flags = ((FLAG_FIXED_DEPTH if fixed_depth else 0) | (FLAG_SQUARE if square else 0) |
                (FLAG_FIELD if field else 0))
+    o.tile_cols = int(tile)
     return o

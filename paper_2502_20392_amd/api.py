@@ -132,7 +132,7 @@ def _auto(run, order, order_hint):
 
 
 def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
-         order_hint=6, square=False, field=False):
+         order_hint=6, square=False, field=False, tile=0):
     """k(x, y) for paths x [lx, d], y [ly, d] (FP64, on the GPU).  Returns a 0-d tensor.
 
     fixed_depth=True, square=True, order=8: the paper's fixed order N = 7 (every
@@ -144,7 +144,7 @@ def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=
     lib = _lib.load()
 
     def run(p):
-        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field)
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field, tile)
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_pair_workspace_size(x.shape[0], y.shape[0], x.shape[1],
                                                 ctypes.byref(o), ctypes.byref(nb)))
@@ -158,7 +158,7 @@ def pair(x, y, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=
 
 
 def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False, ws=None,
-         order_hint=6, square=False, field=False):
+         order_hint=6, square=False, field=False, tile=0):
     """Gram matrix G[i, j] = k(X_i, Y_j); X [nx, lx, d], Y [ny, ly, d].  Y=None: symmetric."""
     X = _check_paths(X, "X", 3)
     sym = Y is None
@@ -170,7 +170,7 @@ def gram(X, Y=None, order=12, tol=None, tail_tol=None, grid=0, fixed_depth=False
     ny, ly, _ = Y.shape
 
     def run(p):
-        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field)
+        o = _lib.make_opts(p, tol, tail_tol, grid, fixed_depth, square, field, tile)
         nb = ctypes.c_size_t()
         _lib.check(lib.sigk_gram_workspace_size(nx, ny, lx, ly, d, int(sym), ctypes.byref(o),
                                                 ctypes.byref(nb)))
@@ -242,15 +242,17 @@ class RaggedPlan:
     """
 
     def __init__(self, offsets, pairs, d, order=12, tol=None, tail_tol=None, grid=0,
-                 fixed_depth=False, device="cuda", square=False, out_index=None):
+                 fixed_depth=False, device="cuda", square=False, out_index=None, tile=0):
         """out_index: optional host int64 [npairs] of distinct output slots (pair p
-        writes out[out_index[p]]; no other element of out is touched)."""
+        writes out[out_index[p]]; no other element of out is touched).  tile: the
+        forward's frontier chunk width (0: the compiled default; see tile_options)."""
         lib = _lib.load()
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         self.d = int(d)
         self.npairs = self.pairs.shape[0]
-        self.opts = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth, square)
+        self.opts = _lib.make_opts(order, tol, tail_tol, grid, fixed_depth, square, tile=tile)
+        self.tile = int(tile)
         h = ctypes.c_void_p()
         _lib.check(lib.sigk_plan_ragged(self.offsets.ctypes.data_as(ctypes.c_void_p),
                                         self.offsets.shape[0] - 1, self.d,
@@ -364,16 +366,26 @@ class RaggedPlan:
         return grad_pool
 
 
+def tile_options(order, d):
+    """The forward work-tile widths compiled for (order, d <= 32): [default,
+    alternative] frontier chunk columns (a tile is 64 grid rows by that many
+    columns)."""
+    lib = _lib.load()
+    return [w for w in (lib.sigk_tile_cols(int(order), int(d), 0),
+                        lib.sigk_tile_cols(int(order), int(d), 1)) if w]
+
+
 class OrderClassPlan:
     """A ragged batch whose pairs run at edge orders of their own: one
-    RaggedPlan per distinct order (a persistent launch each, in sequence on the
-    stream), every class writing its pairs' slots of one output array.
+    RaggedPlan per distinct order (a persistent launch each), every class
+    writing its pairs' slots of one output array.
 
     orders: host int [npairs], each pair's compiled edge order (for example
-    from ``tune.tune_ragged_orders``); grids: optional {order: grid}."""
+    from ``tune.tune_ragged_orders``); grids, tiles: optional {order: grid},
+    {order: tile width} (``tune.tune_class_tiles``)."""
 
     def __init__(self, offsets, pairs, d, orders, tol=None, tail_tol=None, grids=None,
-                 device="cuda"):
+                 device="cuda", tiles=None):
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         orders = np.asarray(orders).reshape(-1)
         if orders.shape[0] != pairs.shape[0]:
@@ -385,7 +397,7 @@ class OrderClassPlan:
             g = (grids or {}).get(p, 0)
             self.plans.append(RaggedPlan(offsets, pairs[idx], d, order=p, tol=tol,
                                          tail_tol=tail_tol, grid=g, device=device,
-                                         out_index=idx))
+                                         out_index=idx, tile=(tiles or {}).get(p, 0)))
         self.cells = sum(pl.cells for pl in self.plans)
         self.classes = {pl.order: pl.npairs for pl in self.plans}
         # launch order: the class with the longest dependency chain first (a

@@ -66,6 +66,9 @@ def build(force: bool = False, jobs: int = 0, verbose: bool = False) -> str:
              ("sigk_estimate.hip", "estimate.o", []), ("sigk_delta.hip", "delta.o", [])]
     for p, d in _variants("SIGK_FWD_VARIANTS"):
         units.append(("sigk_fwd.hip", f"fwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
+    for p, d in _variants("SIGK_FWD_VARIANTS"):
+        units.append(("sigk_fwd.hip", f"fwdt_{p}_{d}.o",
+                      [("SIGK_P", p), ("SIGK_D", d), ("SIGK_ALT", 1)]))
     for p, d in _variants("SIGK_FWDG_VARIANTS"):
         units.append(("sigk_fwd.hip", f"fwd_{p}_{d}.o", [("SIGK_P", p), ("SIGK_D", d)]))
     for p, d in _variants("SIGK_FWDSQ_VARIANTS"):

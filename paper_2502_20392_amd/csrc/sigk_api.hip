@@ -42,6 +42,9 @@ const Variant kFwdTable[] = {SIGK_FWD_VARIANTS(SIGK_V_FWD)};
 #define SIGK_V_BWD(P, D) {P, D, launch_lines_##P##_##D, occupancy_lines_##P##_##D, launch_ckpt_##P##_##D, launch_bwd_##P##_##D, occupancy_ckpt_##P##_##D, occupancy_bwd_##P##_##D},
 const Variant kBwdTable[] = {SIGK_BWD_VARIANTS(SIGK_V_BWD)};
 #undef SIGK_V_BWD
+#define SIGK_V_FWDT(P, D) {P, D, launch_fwdt_##P##_##D, occupancy_fwdt_##P##_##D, nullptr, nullptr, nullptr, nullptr},
+const Variant kFwdTTable[] = {SIGK_FWD_VARIANTS(SIGK_V_FWDT)};
+#undef SIGK_V_FWDT
 #define SIGK_V_FWDSQ(P, D) {P, D, launch_fwdsq_##P##_##D, occupancy_fwdsq_##P##_##D, nullptr, nullptr, nullptr, nullptr},
 const Variant kFwdSqTable[] = {SIGK_FWDSQ_VARIANTS(SIGK_V_FWDSQ)};
 #undef SIGK_V_FWDSQ
@@ -66,7 +69,23 @@ int bucket_of(int64_t d, uint32_t flags) {
     return (d > 32 || (flags & SIGK_FLAG_FIELD)) ? 0 : round_dim(d);
 }
 
-const Variant* find_fwd(int P, int D, uint32_t flags = 0) {
+// Work-tile (frontier chunk) choice of a forward call: 0 or the compiled
+// default chunk of (P, D), or the alternative one (channel buckets > 0,
+// without square truncation).
+bool tile_valid(int P, int D, uint32_t flags, int tile) {
+    if (tile == 0 || tile == fwd_chunk_cols(P, D)) return true;
+    return D > 0 && !(flags & SIGK_FLAG_SQUARE) && tile == alt_chunk_cols(P, D);
+}
+bool alt_tile(int P, int D, int tile) { return D > 0 && tile != 0 && tile != fwd_chunk_cols(P, D); }
+int chunk_of(int P, int D, int tile) { return alt_tile(P, D, tile) ? tile : fwd_chunk_cols(P, D); }
+
+const Variant* find_fwd(int P, int D, uint32_t flags = 0, int tile = 0) {
+    if (!tile_valid(P, D, flags, tile)) return nullptr;
+    if (alt_tile(P, D, tile)) {
+        for (const Variant& v : kFwdTTable)
+            if (v.P == P && v.D == D) return &v;
+        return nullptr;
+    }
     if (D == 0) {
         if (flags & SIGK_FLAG_SQUARE) return nullptr;
         for (const Variant& v : kFwdGTable)
@@ -99,7 +118,19 @@ int g_cus[64] = {0};
 
 // resident workgroups per device for a variant's forward, adjoint or
 // checkpoint kernel (their register and LDS footprints differ)
-enum { kKernelFwd = 0, kKernelBwd = 1, kKernelCkpt = 2, kKernelFwdSq = 3, kKernelLines = 4 };
+enum {
+    kKernelFwd = 0,
+    kKernelBwd = 1,
+    kKernelCkpt = 2,
+    kKernelFwdSq = 3,
+    kKernelLines = 4,
+    kKernelFwdT = 5  // forward with the alternative work tile
+};
+
+int fwd_kind(int P, int D, uint32_t flags, int tile) {
+    return (flags & SIGK_FLAG_SQUARE) ? kKernelFwdSq
+                                      : (alt_tile(P, D, tile) ? kKernelFwdT : kKernelFwd);
+}
 
 int device_wgs(int P, int D, int kind) {
     int dev = 0;
@@ -113,8 +144,9 @@ int device_wgs(int P, int D, int kind) {
         g_cus[dev] = cus;
     }
     int occ = 0;
-    if (kind == kKernelFwd || kind == kKernelFwdSq) {
-        const Variant* v = find_fwd(P, D, kind == kKernelFwdSq ? SIGK_FLAG_SQUARE : 0);
+    if (kind == kKernelFwd || kind == kKernelFwdSq || kind == kKernelFwdT) {
+        const Variant* v = find_fwd(P, D, kind == kKernelFwdSq ? SIGK_FLAG_SQUARE : 0,
+                                    kind == kKernelFwdT ? alt_chunk_cols(P, D) : 0);
         occ = v ? v->occ_fwd() : 0;
     } else {
         const Variant* v = find_bwd(P, D);
@@ -392,12 +424,12 @@ int fwd_pass(const sigk_plan* plan, const double* pool, double* out, char* base,
     a.progress = (int*)(base + plan->o_prog);
     a.hdr = hdr;
     a.trunc_est = est;
-    const Variant* v = find_fwd(plan->P, plan->D, plan->opts.flags);
+    const Variant* v = find_fwd(plan->P, plan->D, plan->opts.flags, plan->opts.tile_cols);
     if (!v) return SIGK_EUNSUPPORTED;
     int grid = plan->opts.grid > 0
                    ? plan->opts.grid
                    : device_wgs(plan->P, plan->D,
-                                (plan->opts.flags & SIGK_FLAG_SQUARE) ? kKernelFwdSq : kKernelFwd);
+                                fwd_kind(plan->P, plan->D, plan->opts.flags, plan->opts.tile_cols));
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     hipError_t e = v->fwd(a, std::max(grid, 1), s);
     if (e == hipSuccess) e = launch_finalize(hdr, est, plan->npairs, budget_of(plan->opts), s);
@@ -425,6 +457,13 @@ void sigk_default_opts(sigk_opts* o) {
 }
 
 int sigk_supported_order(int order) { return round_order(order); }
+
+int sigk_tile_cols(int order, int64_t d, int alternative) {
+    const int P = round_order(order);
+    const int D = bucket_of(d, 0);
+    if (!P || D == 0) return alternative ? 0 : (P ? fwd_chunk_cols(P, 0) : 0);
+    return alternative ? alt_chunk_cols(P, D) : fwd_chunk_cols(P, D);
+}
 
 int sigk_device_grid(int order, int64_t d, int backward) {
     const int P = round_order(order);
@@ -454,7 +493,7 @@ int sigk_gram_workspace_size(int64_t nx, int64_t ny, int64_t lx, int64_t ly, int
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
     const int D = bucket_of(d, op.flags);
-    if (!P || !find_fwd(P, D, op.flags)) return SIGK_EUNSUPPORTED;
+    if (!P || !find_fwd(P, D, op.flags, op.tile_cols)) return SIGK_EUNSUPPORTED;
     *bytes = gram_layout(nx, ny, lx, ly, symmetric, P, D == 0).total;
     return SIGK_OK;
 }
@@ -470,7 +509,7 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
     const int D = bucket_of(d, op.flags);
-    const Variant* v = P ? find_fwd(P, D, op.flags) : nullptr;
+    const Variant* v = P ? find_fwd(P, D, op.flags, op.tile_cols) : nullptr;
     if (!v) return SIGK_EUNSUPPORTED;
     const GramLayout L = gram_layout(nx, ny, lx, ly, symmetric, P, D == 0);
     if (L.nprog > INT32_MAX) return SIGK_EINVAL;  // progress slots are indexed in 32 bits
@@ -511,9 +550,7 @@ int sigk_gram(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t 
         e = launch_delta_gemm(a, s);
         if (e != hipSuccess) return device_error(e);
     }
-    int grid = op.grid > 0 ? op.grid
-                           : device_wgs(P, D, (op.flags & SIGK_FLAG_SQUARE) ? kKernelFwdSq
-                                                                          : kKernelFwd);
+    int grid = op.grid > 0 ? op.grid : device_wgs(P, D, fwd_kind(P, D, op.flags, op.tile_cols));
     grid = (int)std::min<int64_t>(grid, a.ntickets);
     e = v->fwd(a, std::max(grid, 1), s);
     if (e == hipSuccess) e = launch_finalize(hdr, est, L.npairs, budget_of(op), s);
@@ -542,7 +579,7 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
     const int D = round_dim(d);
-    if (!P || !D) return SIGK_EUNSUPPORTED;
+    if (!P || !D || !tile_valid(P, D, op.flags, op.tile_cols)) return SIGK_EUNSUPPORTED;
     if (offsets[0] < 0) return SIGK_EINVAL;
     for (int64_t i = 0; i < npaths; ++i)
         if (offsets[i + 1] < offsets[i] || offsets[i + 1] - offsets[i] > INT32_MAX / 2)
@@ -605,7 +642,8 @@ int sigk_plan_ragged(const int64_t* offsets, int64_t npaths, int64_t d, const in
     // off the end of the launch.  Within a pair the producer always ranks
     // first (its chain is one lag longer), so every wave waits on a wave that
     // is already running.  Ties: more cells first, then pair index.
-    const int64_t lag_fwd = fwd_chunk_cols(P, D) + kWave - 1, lag_adj = chunk_cols(P) + kWave - 1;
+    const int64_t lag_fwd = chunk_of(P, D, op.tile_cols) + kWave - 1,
+                  lag_adj = chunk_cols(P) + kWave - 1;
     auto chain_order = [&](bool reverse) {
         struct Key {
             int64_t chain, cells;
@@ -1040,7 +1078,7 @@ int dev_plan(int64_t npaths, int64_t npairs, int64_t max_len, int64_t pool_point
     const sigk_opts op = opts_or_default(o);
     const int P = round_order(op.order);
     const int D = round_dim(d);
-    if (!P || !D) return SIGK_EUNSUPPORTED;
+    if (!P || !D || !tile_valid(P, D, op.flags, op.tile_cols)) return SIGK_EUNSUPPORTED;
     if (backward && !find_bwd(P, D, op.flags)) return SIGK_EUNSUPPORTED;
     pl.P = P;
     pl.D = D;
@@ -1060,7 +1098,7 @@ int dev_plan(int64_t npaths, int64_t npairs, int64_t max_len, int64_t pool_point
     pl.front_doubles = npairs * pl.M * P;
     pl.snap_doubles = backward ? pl.ntk * pl.M * P : 0;
     pl.ckpt_doubles = backward ? pl.ntk * ckpt_strip_doubles(pl.M, P) : 0;
-    pl.lag_f = fwd_chunk_cols(P, D) + kWave - 1;
+    pl.lag_f = chunk_of(P, D, op.tile_cols) + kWave - 1;
     pl.lag_b = chunk_cols(P) + kWave - 1;
     const int64_t chain_max = std::max<int64_t>(pl.S_max - 1, 0) * std::max(pl.lag_f, pl.lag_b) +
                               pl.M + kWave - 1;

@@ -10,7 +10,9 @@
 // Compiled once per (P, D) variant: -DSIGK_P=<order> -DSIGK_D=<channel bucket>;
 // -DSIGK_SQ=1 builds the square-truncation variant (the paper's fixed-order
 // tile matrix, selected by SIGK_FLAG_SQUARE) under the launcher names
-// launch_fwdsq_P_D / occupancy_fwdsq_P_D.
+// launch_fwdsq_P_D / occupancy_fwdsq_P_D; -DSIGK_ALT=1 the variant with the
+// other frontier chunk width (alt_chunk_cols) as launch_fwdt_P_D /
+// occupancy_fwdt_P_D.
 #include "sigk_strip.h"
 
 #ifndef SIGK_P
@@ -22,12 +24,15 @@
 #ifndef SIGK_SQ
 #define SIGK_SQ 0
 #endif
+#ifndef SIGK_ALT
+#define SIGK_ALT 0
+#endif
 
 namespace sigk {
 
-template <int P, int D, bool SQ>
+template <int P, int D, bool SQ, int CH>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 6 && D <= 8 ? 3 : 1))) fwd_kernel(FwdArgs a) {
-    constexpr int CH = fwd_chunk_cols(P, D), RB = fwd_ring_cols(P, D);
+    constexpr int RB = CH == 64 ? 128 : ring_cols(P);
     __shared__ LdsStrip<P, D, CH, RB> L;
     Acc acc;
     const int lane = lane_id();
@@ -70,21 +75,25 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <=
 #if SIGK_SQ
 #define SIGK_LAUNCH launch_fwdsq_
 #define SIGK_OCC occupancy_fwdsq_
+#elif SIGK_ALT
+#define SIGK_LAUNCH launch_fwdt_
+#define SIGK_OCC occupancy_fwdt_
 #else
 #define SIGK_LAUNCH launch_fwd_
 #define SIGK_OCC occupancy_fwd_
 #endif
+constexpr int kChunk = SIGK_ALT ? alt_chunk_cols(SIGK_P, SIGK_D) : fwd_chunk_cols(SIGK_P, SIGK_D);
 
 hipError_t SIGK_NAME(SIGK_LAUNCH, SIGK_P, SIGK_D)(const FwdArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0>), dim3(grid), dim3(kWave), 0, s,
-                       a);
+    hipLaunchKernelGGL((fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0, kChunk>), dim3(grid),
+                       dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 
 int SIGK_NAME(SIGK_OCC, SIGK_P, SIGK_D)() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0>,
-                                                     kWave, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, fwd_kernel<SIGK_P, SIGK_D, SIGK_SQ != 0, kChunk>, kWave, 0) != hipSuccess)
         return 0;
     return nb;
 }

@@ -60,6 +60,13 @@ __host__ __device__ constexpr int ring_cols(int P) { return P <= 8 ? 128 : 96; }
 __host__ __device__ constexpr int fwd_ring_cols(int P, int D) {
     return fwd_chunk_cols(P, D) == 64 ? 128 : ring_cols(P);
 }
+// The other compiled frontier chunk of a (P, D > 0) forward variant: the
+// work-tile width (64 rows x chunk columns) an autotuner may pick instead of
+// the default, 32 where the default is 64 and 64 where it is 32.  The same
+// (P, D) list as SIGK_FWD_VARIANTS is compiled with it (launch_fwdt_P_D).
+__host__ __device__ constexpr int alt_chunk_cols(int P, int D) {
+    return fwd_chunk_cols(P, D) == 64 ? 32 : 64;
+}
 
 // Per-pair geometry for table mode (ragged batches).  Offsets in elements.
 struct PairDesc {
@@ -198,6 +205,11 @@ int device_error(hipError_t e);
 SIGK_FWD_VARIANTS(SIGK_DECL_FWD)
 SIGK_FWDG_VARIANTS(SIGK_DECL_FWD)
 #undef SIGK_DECL_FWD
+#define SIGK_DECL_FWDT(P, D) \
+    hipError_t launch_fwdt_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
+    int occupancy_fwdt_##P##_##D();
+SIGK_FWD_VARIANTS(SIGK_DECL_FWDT)
+#undef SIGK_DECL_FWDT
 #define SIGK_DECL_FWDSQ(P, D) \
     hipError_t launch_fwdsq_##P##_##D(const FwdArgs& a, int grid, hipStream_t s); \
     int occupancy_fwdsq_##P##_##D();

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .api import RaggedPlan, counters, pair
+from .api import RaggedPlan, counters, pair, tile_options
 
 _DEF_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sigk_tune.json")
 
@@ -80,7 +80,10 @@ def _grid_candidates(order, d):
 
 
 def tune_ragged(pool, offsets, pairs, hint=6, reps=2, tol=None, use_cache=True):
-    """Tune a ragged batch.  Returns {"order", "grid", "ms", "status"}."""
+    """Tune a ragged batch: the edge order (the truncation budget), then the
+    work tile (frontier chunk width, both compiled options) and the persistent
+    grid by timing.  Returns {"order", "tile", "grid", "ms", "status",
+    "trials"}."""
     d = pool.shape[1]
     key = "ragged:" + _digest(offsets, pairs, pool) + f":{hint}:{tol}"
     if use_cache:
@@ -98,15 +101,43 @@ def tune_ragged(pool, offsets, pairs, hint=6, reps=2, tol=None, use_cache=True):
             break
         status = st
     best = None
-    for g in _grid_candidates(order, d):
-        plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, grid=g, device=pool.device)
-        out = torch.empty(plan.npairs, dtype=torch.float64, device=pool.device)
-        ms = _time(lambda: plan.run(pool, out), reps)
-        if best is None or ms < best["ms"]:
-            best = {"order": order, "grid": g, "ms": ms, "status": status}
+    trials = []
+    for tile in tile_options(order, d):
+        for g in _grid_candidates(order, d):
+            plan = RaggedPlan(offsets, pairs, d, order=order, tol=tol, grid=g, device=pool.device,
+                              tile=tile)
+            out = torch.empty(plan.npairs, dtype=torch.float64, device=pool.device)
+            ms = _time(lambda: plan.run(pool, out), reps)
+            trials.append({"tile": tile, "grid": g, "ms": ms})
+            if best is None or ms < best["ms"]:
+                best = {"order": order, "tile": tile, "grid": g, "ms": ms, "status": status}
+    best["trials"] = trials
     if use_cache:
         _store(key, best)
     return best
+
+
+def tune_class_tiles(pool, offsets, pairs, orders, reps=2, tol=None):
+    """The work tile of each order class of a per-pair-order batch (see
+    tune_ragged_orders), by timing each class's plan with both compiled tile
+    widths.  Returns ({order: tile}, trials)."""
+    d = pool.shape[1]
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    orders = np.asarray(orders).reshape(-1)
+    tiles, trials = {}, []
+    for p in sorted(set(int(o) for o in orders)):
+        idx = np.nonzero(orders == p)[0]
+        best = None
+        for tile in tile_options(p, d):
+            plan = RaggedPlan(offsets, pairs[idx], d, order=p, tol=tol, device=pool.device,
+                              tile=tile)
+            out = torch.empty(plan.npairs, dtype=torch.float64, device=pool.device)
+            ms = _time(lambda: plan.run(pool, out), reps)
+            trials.append({"order": p, "tile": tile, "ms": ms})
+            if best is None or ms < best[1]:
+                best = (tile, ms)
+        tiles[p] = best[0]
+    return tiles, trials
 
 
 def tune_ragged_orders(pool, offsets, pairs, hint=4, tol=None, tail_tol=None):

@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
     for must in ("sigk_pair", "sigk_gram", "sigk_plan_ragged", "sigk_plan_run",
                  "sigk_plan_backward", "sigk_read_status"):
         assert must in names
-    assert len(names) == 34
+    assert len(names) == 35
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -252,6 +252,32 @@ def test_plan_ticket_order(lib, seed):
             check_ticket_order([tuple(t) for t in buf[: n.value]], strips, adjoint)
     finally:
         lib.sigk_plan_destroy(plan)
+
+
+def test_tile_options(lib):
+    """Forward work tiles: the default and the other compiled chunk width per
+    (order, d); plans and Gram sizes accept those two and refuse others."""
+    for order, d, want in ((5, 8, (64, 32)), (6, 8, (32, 64)), (10, 16, (64, 32)),
+                           (12, 32, (32, 64)), (24, 8, (32, 64))):
+        assert (lib.sigk_tile_cols(order, d, 0), lib.sigk_tile_cols(order, d, 1)) == want
+    assert lib.sigk_tile_cols(5, 40, 1) == 0  # d > 32: the field sweep's tile only
+    assert lib.sigk_tile_cols(30, 8, 0) == 0
+    b = ctypes.c_size_t()
+    for tile, rc in ((0, 0), (32, 0), (64, 0), (16, -4), (48, -4)):
+        o = _lib.make_opts(order=8, tile=tile)
+        assert lib.sigk_gram_workspace_size(3, 3, 100, 100, 4, 0, ctypes.byref(o),
+                                            ctypes.byref(b)) == rc, tile
+        plan = ctypes.c_void_p()
+        offs = np.array([0, 50, 120], dtype=np.int64)
+        prs = np.array([[0, 1]], dtype=np.int32)
+        r = lib.sigk_plan_ragged(offs.ctypes.data, 2, 4, prs.ctypes.data, 1, ctypes.byref(o),
+                                 ctypes.byref(plan))
+        assert r == rc, tile
+        if r == 0:
+            lib.sigk_plan_destroy(plan)
+    sq = _lib.make_opts(order=8, square=True, tile=64)
+    assert lib.sigk_gram_workspace_size(3, 3, 100, 100, 4, 0, ctypes.byref(sq),
+                                        ctypes.byref(b)) == -4
 
 
 def test_plan_output_slots(lib):
