@@ -152,10 +152,17 @@ def extras(torch, sk, dev, only=""):
             tried.append({"order": order, "status": st})
             if not st & _lib.WARN_TRUNC:
                 break
-        ms = timed(lambda: sk.gram(X, order=order), torch)
+        # work tile: both compiled chunk widths timed, the faster kept
+        tiles = []
+        for tile in sk.api.tile_options(order, X.shape[2]):
+            tiles.append({"tile": tile, "ms": timed(lambda: sk.gram(X, order=order, tile=tile),
+                                                    torch)})
+        tile = min(tiles, key=lambda t: t["ms"])["tile"]
+        ms = timed(lambda: sk.gram(X, order=order, tile=tile), torch)
         c = sk.counters()
         res[name] = {"cells_per_s": c["cells"] / (ms / 1e3), "ms": ms, "order": order,
-                     "orders_tried": tried, "fp64_frac": frac(c["flops"], ms),
+                     "orders_tried": tried, "tile": tile, "tile_trials": tiles,
+                     "fp64_frac": frac(c["flops"], ms),
                      "status": c["status"], "trunc_est": c["trunc_est"]}
 
     for name, sig in (("gram64_len1024_d16_sigma1", 1.0), ("gram64_len1024_d16_sigma4", 4.0)):
