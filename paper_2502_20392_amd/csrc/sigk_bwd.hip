@@ -306,15 +306,21 @@ struct StripBwd {
                 return;
             }
         }
-        segment<Q>(q, rough, t0, t1);
+        if (t0 >= kWave && t1 <= m - 1)
+            segment<Q, true>(q, rough, t0, t1);
+        else
+            segment<Q, false>(q, rough, t0, t1);
     }
 
     // One segment [t0, t1) of kCkptEvery steps: recompute it forward from its
     // checkpoint, storing each step's bottom edges, then run the adjoint steps
     // last to first.  Q >= 0: depth fixed at compile time (== q); Q < 0: q.
     // rough: the left edges are stored too (second half of the scratch) and
-    // read back instead of recovered from the right edges.
-    template <int Q>
+    // read back instead of recovered from the right edges.  IN: every cell
+    // of the segment is inside the strip's columns and none is in its first
+    // or last column (t0 >= 64, t1 <= m - 1), so the per-lane tests for the
+    // row ends, the corner seed and the block lines drop out.
+    template <int Q, bool IN>
     __device__ void segment(int q, bool rough, int t0, int t1) {
         const int lane = lane_id();
         const int CH = ACH;
@@ -334,7 +340,7 @@ struct StripBwd {
             const double* bsrc = &L.bin[(t % CH) * P];
 #pragma unroll
             for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
-            if (col == 0) {
+            if (!IN && col == 0) {
                 if (left != nullptr && lane_ok) {
                     const double* lp = left + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
@@ -362,7 +368,7 @@ struct StripBwd {
             double An[P], Bn[P];
             cell_map<P>(A, B, c0 + c1, An, Bn, Q >= 0 ? Q : q, R);
             // past the end of the row B keeps the row's last right edge
-            const bool live = col < m;
+            const bool live = IN || col < m;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 B[i] = live ? Bn[i] : B[i];
@@ -376,7 +382,7 @@ struct StripBwd {
                                  cell_flops(P, Q >= 0 ? Q : q, a.d));
         for (int t = t1 - 1; t >= t0; --t) {
             const int col = t - lane;
-            const bool act = lane_ok && col >= 0 && col < m;
+            const bool act = lane_ok && (IN || (col >= 0 && col < m));
             {
                 const unsigned cnt = (unsigned)__builtin_popcountll(ballot(act));
                 *cells += cnt;
@@ -412,7 +418,7 @@ struct StripBwd {
 #pragma unroll
                 for (int i = 0; i < P; ++i) lAo[i] = shift_down(lAprev[i], lsrc[i]);
             } else {
-                const bool corner = col == m - 1;
+                const bool corner = !IN && col == m - 1;
                 double f = seed_scale;
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
@@ -422,7 +428,7 @@ struct StripBwd {
                     f = f * R(i + 1);
                 }
             }
-            if (col == m - 1) {
+            if (!IN && col == m - 1) {
                 if (right_in && lane_ok) {
                     const double* lp = lamv + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
@@ -434,8 +440,8 @@ struct StripBwd {
             }
             // column 0 on a left line: the left edge is recovered like any
             // other (it is the right edge of the block to the left)
-            const bool axis = col == 0 && left == nullptr;
-            const bool recover = !rough && col < m;  // rough: B is the stored left edge
+            const bool axis = !IN && col == 0 && left == nullptr;
+            const bool recover = !rough && (IN || col < m);  // rough: B is the stored left edge
             double lA[P], lB[P];
             double gc;
             if constexpr (Q >= 0)
@@ -443,7 +449,7 @@ struct StripBwd {
             else
                 gc = cell_adjoint<P>(A, B, c, q, axis, recover, lAo, lBst, lA, lB, R);
             if (!act) gc = 0.0;
-            if (left_out && act && col == 0) {
+            if (!IN && left_out && act && col == 0) {
                 double* lp = lamv + ((int64_t)s * kWave + lane) * P;
 #pragma unroll
                 for (int i = 0; i < P; ++i) lp[i] = lB[i];
@@ -456,7 +462,7 @@ struct StripBwd {
                     double& gv = L.gx[ch * ARB + ri];
                     gv = fma(gc, dy[ch], gv);
                 }
-                if (lane == 0) {
+                if (has_below && lane == 0) {
 #pragma unroll
                     for (int i = 0; i < P; ++i) L.lout[(col % CH) * P + i] = lA[i];
                 }
@@ -516,7 +522,7 @@ struct StripBwd {
             if constexpr (P <= 12)
                 segment_at_depth<0>(q, rough, t0, t1);
             else
-                segment<-1>(q, rough, t0, t1);
+                segment<-1, false>(q, rough, t0, t1);
             if (t0 < m && (t0 % CH) == 0) flush_cols(t0, min(t0 + CH, m));
         }
         // dL/d(dy_l) of this lane's row
