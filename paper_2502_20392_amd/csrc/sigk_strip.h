@@ -72,9 +72,11 @@ struct LdsStrip {
     // D > 0: increments of x, [channel][ring slot]; D = 0: the chunk's cell
     // coefficients, [step][lane] (no LDS beyond what D > 0 needs: every byte
     // more costs the order-5 kernel a wave per CU)
-    double dx[D > 0 ? D * RB : CH * kWave];
+    // (bin first: its rows are then addressed from one register with the
+    // instructions' immediate offsets)
     double bin[CH * P];   // bottom edges of the current chunk (lane 0)
     double tout[CH * P];  // top edges of the top lane, current chunk
+    double dx[D > 0 ? D * RB : CH * kWave];
     float nrm2[D > 0 ? RB : 1];     // |dx_k|^2 of the same columns, rounded up
 };
 
@@ -550,9 +552,20 @@ struct StripCtx {
             } else if constexpr (kAhead) {
                 // increments of the next step's column, consumed after the map
                 c = cn;
-                const int ri = ring_slot_of<RB>(t + 1 - lane);
+                if constexpr ((RB & (RB - 1)) == 0) {
+                    // byte offset of the slot: a uniform step part minus a
+                    // lane part, masked (two vector instructions)
+                    const unsigned off = ((unsigned)(t + 1) * 8u - (unsigned)lane * 8u) &
+                                         (unsigned)((RB - 1) * 8);
+                    const char* base = (const char*)L.dx + off;
 #pragma unroll
-                for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * RB + ri];
+                    for (int ch = 0; ch < D; ++ch)
+                        dxv[ch] = *(const double*)(base + (size_t)ch * RB * 8);
+                } else {
+                    const int ri = ring_slot_of<RB>(t + 1 - lane);
+#pragma unroll
+                    for (int ch = 0; ch < D; ++ch) dxv[ch] = L.dx[ch * RB + ri];
+                }
             } else {
                 prefetch(t);
                 c = cn;
@@ -583,7 +596,9 @@ struct StripCtx {
             }
             if constexpr (BLK) vline_hook(col, act);
             if (has_above && lane == kWave - 1 && act) {
-                double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
+                // the top lane's column t - 63, a uniform address
+                const unsigned tc = (unsigned)(t - (kWave - 1));
+                double* dst = &L.tout[(tc % (unsigned)CH) * P];
                 lds_copy<P>(dst, An);
             }
             return;
