@@ -336,10 +336,6 @@ struct StripBwd {
         }
         for (int t = t0; t < t1; ++t) {
             const int col = t - lane;
-            double A[P];
-            const double* bsrc = &L.bin[(t % CH) * P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
             if (!IN && col == 0) {
                 if (left != nullptr && lane_ok) {
                     const double* lp = left + ((int64_t)s * kWave + lane) * P;
@@ -350,14 +346,6 @@ struct StripBwd {
                     for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
                 }
             }
-            double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
-#pragma unroll
-            for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
-            if (rough) {
-                double* bdst = dst + kCkptEvery * P * kWave;
-#pragma unroll
-                for (int i = 0; i < P; ++i) bdst[i * kWave + lane] = B[i];
-            }
             const int ri = ring_slot_of<ARB>(col);
             double c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -365,8 +353,33 @@ struct StripBwd {
                 c0 = fma(dy[ch], L.dx[ch * ARB + ri], c0);
                 c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ARB + ri], c1);
             }
-            double An[P], Bn[P];
-            cell_map<P>(A, B, c0 + c1, An, Bn, Q >= 0 ? Q : q, R);
+            const double c = c0 + c1;
+            double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
+            if (rough) {
+                double* bdst = dst + kCkptEvery * P * kWave;
+#pragma unroll
+                for (int i = 0; i < P; ++i) bdst[i * kWave + lane] = B[i];
+            }
+            double A[P], An[P], Bn[P];
+            const double* bsrc = &L.bin[(t % CH) * P];
+            if constexpr (Q >= 0 && P <= 12) {
+                // the map in two halves, as in the forward sweep (the same
+                // sums in the same order): the B-only half covers the latency
+                // of the lane shift that delivers A
+                SplitMap<P, Q, false> S;
+                S.pre(B, c, Bn, R);
+#pragma unroll
+                for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
+#pragma unroll
+                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+                S.post(A, An, Bn, R);
+            } else {
+#pragma unroll
+                for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
+#pragma unroll
+                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+                cell_map<P>(A, B, c, An, Bn, Q >= 0 ? Q : q, R);
+            }
             // past the end of the row B keeps the row's last right edge
             const bool live = IN || col < m;
 #pragma unroll
