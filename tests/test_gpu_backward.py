@@ -71,6 +71,26 @@ def test_gradient_several_chunks(dev, order, d):
     assert sk().counters()["status"] == 0
 
 
+
+@pytest.mark.parametrize("lx", [81, 82, 83, 97, 98])
+@pytest.mark.parametrize("order", [5, 10])
+def test_gradient_interior_segment_bounds(dev, lx, order):
+    """Rows of m = lx - 1 cells around multiples of the 16-step checkpoint
+    segment, so that the last segment whose cells all lie at least one column
+    from either row end stops just before, at and after the row's last
+    column; two strips, the upper one partial (99 rows)."""
+    g = synth.rng(4700 + lx + order)
+    step = 0.002 if order < 10 else 0.01
+    x = np.cumsum(g.normal(size=(lx, 3)) * step, axis=0)
+    y = np.cumsum(g.normal(size=(100, 3)) * step, axis=0)
+    k0, gx0, gy0 = oracle.grad(x, y)
+    k, gx, gy = gpu_pair_grad(x, y, dev, order=order)
+    sc = max(1.0, np.abs(gx0).max(), np.abs(gy0).max())
+    assert abs(k - k0) <= 1e-12 * max(1, abs(k0))
+    assert np.abs(gx - gx0).max() <= 1e-10 * sc
+    assert np.abs(gy - gy0).max() <= 1e-10 * sc
+    assert sk().counters()["status"] == 0
+
 def test_degenerate_paths_in_gradient_batch(dev):
     """A ragged batch mixing paths of 0, 1 and 2 points with longer ones: pairs
     with a path of at most one point have k = 1 and contribute nothing to the
