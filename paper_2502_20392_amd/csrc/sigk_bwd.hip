@@ -141,6 +141,51 @@ __global__ void __launch_bounds__(kWave)
     }
 }
 
+// A workgroup's segment scratch as a buffer resource: rows of 64 doubles,
+// one per lane.  The lane's column goes in the vector offset and the row
+// (step and coefficient) in the scalar offset, so stepping through the rows
+// costs no vector instructions.  Every access is range-checked against the
+// buffer's size by the hardware.
+struct SegScratch {
+    using u32x2 = unsigned int __attribute__((__vector_size__(8)));
+    __amdgpu_buffer_rsrc_t r;
+    __device__ void init(double* p, int rows) {
+        const uint64_t a = (uint64_t)p;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        r = __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
+                                              rows * kWave * 8, 0x00020000);
+    }
+    __device__ __forceinline__ void store(int row, double v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, lane_id() * 8,
+                                              row * (kWave * 8), 0);
+    }
+    __device__ __forceinline__ double load(int row) const {
+        return __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_id() * 8, row * (kWave * 8), 0));
+    }
+};
+
+// Byte offset of a lane's slot in a ring of ARB columns, stepped one column
+// at a time (two or three vector instructions instead of a division).
+template <int ARB>
+struct RingPos {
+    unsigned b;
+    __device__ __forceinline__ void set(int col) { b = (unsigned)ring_slot_of<ARB>(col) * 8u; }
+    __device__ __forceinline__ void next() {
+        if constexpr ((ARB & (ARB - 1)) == 0)
+            b = (b + 8u) & (unsigned)((ARB - 1) * 8);
+        else
+            b = b + 8u == (unsigned)(ARB * 8) ? 0u : b + 8u;
+    }
+    __device__ __forceinline__ void prev() {
+        if constexpr ((ARB & (ARB - 1)) == 0)
+            b = (b - 8u) & (unsigned)((ARB - 1) * 8);
+        else
+            b = b == 0u ? (unsigned)((ARB - 1) * 8) : b - 8u;
+    }
+};
+
 template <int P, int D>
 struct LdsBwd {
     // Columns per cotangent-frontier chunk and of the increment rings.  At
@@ -156,11 +201,29 @@ struct LdsBwd {
     static constexpr int ARB = ACH == 64 ? 128 : 96;
     static_assert(ARB >= ACH + kWave - 1,
                   "the rings must hold a chunk and the 63 columns before it");
-    double dx[D * ARB];      // increments of x by ring slot
-    double gx[D * ARB];      // dL/d(dx) being accumulated, by ring slot
+    // (the edge rows first: one address register with the instructions'
+    // immediate offsets reaches a whole row)
     double bin[ACH * P];    // primal bottom edges (lane 0) of a chunk
     double lin[2 * ACH * P];  // top-edge cotangents (top lane), 2 chunks
     double lout[ACH * P];   // bottom-edge cotangents (lane 0), 1 chunk
+    // increments of x and dL/d(dx) being accumulated, by ring slot,
+    // interleaved per channel: [channel][dx, gx][slot].  A channel's rows lie
+    // 2 ARB doubles apart, a multiple of 512 bytes, so one address register
+    // and offsets in 512-byte units reach every channel's slot.
+    double xg[D * 2 * ARB];
+    static_assert((2 * ARB * 8) % 512 == 0 && (ACH * P * 4 * 8) % 512 == 0,
+                  "channel rows on 512-byte boundaries");
+    __device__ __forceinline__ double& dx(int ch, int slot) { return xg[2 * ch * ARB + slot]; }
+    __device__ __forceinline__ double& gx(int ch, int slot) {
+        return xg[(2 * ch + 1) * ARB + slot];
+    }
+    // the same by a RingPos byte offset
+    __device__ __forceinline__ double& dx_at(int ch, const RingPos<ARB>& p) {
+        return *(double*)((char*)&xg[2 * ch * ARB] + p.b);
+    }
+    __device__ __forceinline__ double& gx_at(int ch, const RingPos<ARB>& p) {
+        return *(double*)((char*)&xg[(2 * ch + 1) * ARB] + p.b);
+    }
 };
 
 template <int P, int D>
@@ -177,7 +240,7 @@ struct StripBwd {
     double gy[D];
     Recip<P, false> R;  // scalar or rematerialised constants: registers are scarce here
     int dx_lo, lin_lo, bin_chunk;
-    double* scratch;
+    SegScratch scr;  // kCkptEvery x P recomputed bottom-edge rows, then as many left-edge rows
     unsigned long long* cells;  // per-workgroup tallies (cells, algorithmic flops)
     unsigned long long* flops;
     const double* ck;
@@ -215,8 +278,7 @@ struct StripBwd {
                 const double* xp = g.x + (int64_t)col * a.d;
 #pragma unroll
                 for (int ch = 0; ch < D; ++ch)
-                    L.dx[ch * ARB + ring_slot_of<ARB>(col)] =
-                        ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
+                    L.dx(ch, ring_slot_of<ARB>(col)) = ch < a.d ? xp[a.d + ch] - xp[ch] : 0.0;
             }
             dx_lo = c0;
             __syncthreads();
@@ -278,8 +340,8 @@ struct StripBwd {
             double* gp = gxp + (int64_t)col * a.d;
 #pragma unroll
             for (int ch = 0; ch < D; ++ch) {
-                if (ch < a.d) atomicAdd(&gp[ch], L.gx[ch * ARB + sl]);
-                L.gx[ch * ARB + sl] = 0.0;
+                if (ch < a.d) atomicAdd(&gp[ch], L.gx(ch, sl));
+                L.gx(ch, sl) = 0.0;
             }
         }
         (void)CH;
@@ -334,6 +396,8 @@ struct StripBwd {
                 Ac[i] = src[(P + i) * kWave + lane];
             }
         }
+        RingPos<ARB> rp;
+        rp.set(t0 - lane);
         for (int t = t0; t < t1; ++t) {
             const int col = t - lane;
             if (!IN && col == 0) {
@@ -346,19 +410,18 @@ struct StripBwd {
                     for (int i = 0; i < P; ++i) B[i] = i == 0 ? 1.0 : 0.0;
                 }
             }
-            const int ri = ring_slot_of<ARB>(col);
             double c0 = 0.0, c1 = 0.0;
 #pragma unroll
             for (int ch = 0; ch < D; ch += 2) {
-                c0 = fma(dy[ch], L.dx[ch * ARB + ri], c0);
-                c1 = fma(dy[ch + 1], L.dx[(ch + 1) * ARB + ri], c1);
+                c0 = fma(dy[ch], L.dx_at(ch, rp), c0);
+                c1 = fma(dy[ch + 1], L.dx_at(ch + 1, rp), c1);
             }
+            rp.next();
             const double c = c0 + c1;
-            double* dst = scratch + (int64_t)(t - t0) * (P * kWave);
+            const int row0 = (t - t0) * P;
             if (rough) {
-                double* bdst = dst + kCkptEvery * P * kWave;
 #pragma unroll
-                for (int i = 0; i < P; ++i) bdst[i * kWave + lane] = B[i];
+                for (int i = 0; i < P; ++i) scr.store(kCkptEvery * P + row0 + i, B[i]);
             }
             double A[P], An[P], Bn[P];
             const double* bsrc = &L.bin[(t % CH) * P];
@@ -371,13 +434,13 @@ struct StripBwd {
 #pragma unroll
                 for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
 #pragma unroll
-                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+                for (int i = 0; i < P; ++i) scr.store(row0 + i, A[i]);
                 S.post(A, An, Bn, R);
             } else {
 #pragma unroll
                 for (int i = 0; i < P; ++i) A[i] = shift_up(Ac[i], bsrc[i]);
 #pragma unroll
-                for (int i = 0; i < P; ++i) dst[i * kWave + lane] = A[i];
+                for (int i = 0; i < P; ++i) scr.store(row0 + i, A[i]);
                 cell_map<P>(A, B, c, An, Bn, Q >= 0 ? Q : q, R);
             }
             // past the end of the row B keeps the row's last right edge
@@ -393,6 +456,7 @@ struct StripBwd {
         const unsigned long long fl =
             (unsigned long long)(adjoint_flops(P, Q >= 0 ? Q : q, a.d) +
                                  cell_flops(P, Q >= 0 ? Q : q, a.d));
+        rp.set(t1 - 1 - lane);
         for (int t = t1 - 1; t >= t0; --t) {
             const int col = t - lane;
             const bool act = lane_ok && (IN || (col >= 0 && col < m));
@@ -401,22 +465,20 @@ struct StripBwd {
                 *cells += cnt;
                 *flops += cnt * fl;
             }
-            const double* src = scratch + (int64_t)(t - t0) * (P * kWave);
+            const int row0 = (t - t0) * P;
             double A[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) A[i] = src[i * kWave + lane];
+            for (int i = 0; i < P; ++i) A[i] = scr.load(row0 + i);
             if (rough) {
-                const double* bsrc = src + kCkptEvery * P * kWave;
 #pragma unroll
-                for (int i = 0; i < P; ++i) B[i] = bsrc[i * kWave + lane];
+                for (int i = 0; i < P; ++i) B[i] = scr.load(kCkptEvery * P + row0 + i);
             }
-            const int ri = ring_slot_of<ARB>(col);
             double dxv[D];
             double c0 = 0.0, c1 = 0.0;
 #pragma unroll
             for (int ch = 0; ch < D; ch += 2) {
-                dxv[ch] = L.dx[ch * ARB + ri];
-                dxv[ch + 1] = L.dx[(ch + 1) * ARB + ri];
+                dxv[ch] = L.dx_at(ch, rp);
+                dxv[ch + 1] = L.dx_at(ch + 1, rp);
                 c0 = fma(dy[ch], dxv[ch], c0);
                 c1 = fma(dy[ch + 1], dxv[ch + 1], c1);
             }
@@ -472,14 +534,16 @@ struct StripBwd {
             if (act) {
 #pragma unroll
                 for (int ch = 0; ch < D; ++ch) {
-                    double& gv = L.gx[ch * ARB + ri];
+                    double& gv = L.gx_at(ch, rp);
                     gv = fma(gc, dy[ch], gv);
                 }
                 if (has_below && lane == 0) {
+                    // lane 0's column is t (a uniform address)
 #pragma unroll
-                    for (int i = 0; i < P; ++i) L.lout[(col % CH) * P + i] = lA[i];
+                    for (int i = 0; i < P; ++i) L.lout[((unsigned)t % (unsigned)CH) * P + i] = lA[i];
                 }
             }
+            rp.prev();
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 lBst[i] = lB[i];
@@ -507,10 +571,7 @@ struct StripBwd {
                          : 0.0;
             gy[ch] = 0.0;
         }
-        for (int e = lane; e < D * ARB; e += kWave) {
-            L.gx[e] = 0.0;
-            L.dx[e] = 0.0;
-        }
+        for (int e = lane; e < 2 * D * ARB; e += kWave) L.xg[e] = 0.0;
         const int top = CH * ((m + CH - 1) / CH);
         dx_lo = kCkptEvery * ((m + kCkptEvery - 1) / kCkptEvery);
         lin_lo = top;
@@ -579,7 +640,7 @@ __global__ void __launch_bounds__(kWave) bwd_kernel(BwdArgs b) {
             if (strip * kWave >= g.n) continue;  // the top block row has fewer strips
         }
         StripBwd<P, D> S(b, g, L, strip);
-        S.scratch = scratch;
+        S.scr.init(scratch, 2 * kCkptEvery * P);
         S.cells = &cells;
         S.flops = &flops;
         S.ck = b.ckpt + g.ckpt + (int64_t)strip * ckpt_strip_doubles(g.m, P);
