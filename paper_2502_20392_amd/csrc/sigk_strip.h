@@ -349,7 +349,7 @@ struct StripCtx {
     const double* left = nullptr;
     bool below_line = false;
     double* vl = nullptr;
-    int vcnt = 0;  // steps until the lane's column is the last of a block column
+    int vnext = 0;  // step at which lane 0 reaches the last column of its block column
 
     __device__ StripCtx(const FwdArgs& a_, Geo& g_, LdsStrip<P, D, CH, RB>& L_, Acc& acc_, int s_)
         : a(a_), g(g_), L(L_), acc(acc_), s(s_) {}
@@ -496,16 +496,27 @@ struct StripCtx {
 
     // After the cell of column col (BLK, with vl): at the last column of a
     // block column (except the grid's last) keep the cell's right edge.
-    __device__ __forceinline__ void vline_hook(int col, bool act) {
+    __device__ __forceinline__ void vline_hook(int t, int col, bool act) {
         if (vl == nullptr) return;
-        if (vcnt == 0 && act && col + 1 < g.m) {
-            const int J = (col + 1) / a.blk.cb;
+        const int cb = a.blk.cb;
+        bool mine;
+        if (cb >= kWave) {
+            // at most one lane per step, in the 64 steps after lane 0 reaches
+            // the last column of a block column: a uniform test per step
+            const int w = t - vnext;
+            if ((unsigned)w >= (unsigned)kWave) return;
+            if (w == kWave - 1) vnext += cb;
+            mine = lane_id() == w;
+        } else {
+            mine = (col + 1) % cb == 0;
+        }
+        if (mine && act && col + 1 < g.m) {
+            const int J = (col + 1) / cb;
             double* dst =
                 vl + ((int64_t)(J - 1) * a.blk.n + (int64_t)s * kWave + lane_id()) * P;
 #pragma unroll
             for (int i = 0; i < P; ++i) dst[i] = B[i];
         }
-        vcnt = vcnt == 0 ? a.blk.cb - 1 : vcnt - 1;
     }
 
     // Cell coefficient c = <dx_col, dy_row> of step t into cn.  For small
@@ -594,7 +605,7 @@ struct StripCtx {
                 B[i] = Bn[i];
                 Ac[i] = An[i];
             }
-            if constexpr (BLK) vline_hook(col, act);
+            if constexpr (BLK) vline_hook(t, col, act);
             if (has_above && lane == kWave - 1 && act) {
                 // the top lane's column t - 63, a uniform address
                 const unsigned tc = (unsigned)(t - (kWave - 1));
@@ -642,7 +653,7 @@ struct StripCtx {
             B[i] = Bn[i];
             Ac[i] = An[i];
         }
-        if constexpr (BLK) vline_hook(col, act);
+        if constexpr (BLK) vline_hook(t, col, act);
         if (has_above && lane == kWave - 1 && act) {
             double* dst = &L.tout[((unsigned)col % (unsigned)CH) * P];
 #pragma unroll
@@ -724,7 +735,7 @@ struct StripCtx {
         has_above = row0 + kWave < g.n;
         nvalid = (unsigned)nrows;
         if constexpr (BLK) {
-            if (vl != nullptr) vcnt = (a.blk.cb - 1 + lane) % a.blk.cb;
+            vnext = a.blk.cb - 1;
         }
         R.init();
         const int l = row0 + lane;
